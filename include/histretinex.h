@@ -1,0 +1,176 @@
+/*
+ * histretinex.h -- C ABI of the MI355X (gfx950) HistRetinex library.
+ *
+ * HistRetinex (Zhao et al., arXiv 2510.21100) enhances a low-light image in
+ * the histogram domain: it builds the histogram of the HSV value channel S
+ * and of its gradient image (Sec. II, Eq. 3; Alg. 1 initialisation), fits
+ * illumination and reflectance histograms to it by the alternating updates of
+ * Eqs. (11)-(15) (Alg. 1), brightens the illumination locations and forms the
+ * enhanced target histogram (Eqs. 17-20), and maps every pixel to that target
+ * by histogram matching (end of Sec. III-C).
+ *
+ * Conventions shared by every call
+ *  - Images are HWC interleaved RGB in device memory: 8-bit images are uint8
+ *    (bits = 8, 256 levels), 10-bit images are uint16 holding values 0..1023
+ *    (bits = 10, 1024 levels).  Rows are row_stride_bytes apart; a stride of
+ *    exactly 3*width*element_size with a 16-byte aligned base takes the
+ *    vectorised path, any other stride >= that takes a slower scalar path.
+ *  - Widths up to 24576 (8-bit) / 12288 (10-bit) are supported.
+ *  - bins must equal 2^bits.
+ *  - All device pointers are caller-owned; the library never frees them.
+ *  - Every compute call is asynchronous and ordered on `stream` (a
+ *    hipStream_t passed as void*, NULL = the default stream).  Arguments are
+ *    validated on the host before anything is enqueued: on any error the call
+ *    returns a status, enqueues nothing and records a message readable through
+ *    hr_last_error() (thread-local).
+ *  - Data faults found on the device (a 10-bit value above 1023, histograms
+ *    whose mass disagrees with npix) cannot be returned as a status: the value
+ *    is clamped / the histogram mass is used, and a sticky bit is set in the
+ *    workspace flags, read with hr_get_flags() after the stream is synchronised.
+ *  - A workspace holds device scratch, counters and cached launch graphs.  Use
+ *    one workspace per stream: two calls in flight on one workspace race.
+ *
+ * Histograms are in the paper's count units: hist_v[k] is the number of pixels
+ * whose value channel equals k, illum/refl/target sum to the pixel count.
+ */
+#ifndef HISTRETINEX_H
+#define HISTRETINEX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HR_ABI_VERSION 1
+
+typedef enum {
+  HR_OK = 0,
+  HR_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad parameter value      */
+  HR_ERR_UNSUPPORTED = 2, /* valid but outside what this build implements    */
+  HR_ERR_WORKSPACE = 3,   /* workspace too small for the request              */
+  HR_ERR_DEVICE = 4       /* a HIP runtime call failed; see hr_last_error()   */
+} hr_status;
+
+/* sticky device flags (hr_get_flags) */
+#define HR_FLAG_VALUE_CLAMPED 0x1u /* a 10-bit channel value > 1023 was read  */
+#define HR_FLAG_HIST_MASS 0x2u     /* histogram mass != npix in hr_solve       */
+
+/* One RGB image.  data: device pointer to the first pixel. */
+typedef struct {
+  const void* data;
+  int32_t width;
+  int32_t height;
+  int64_t row_stride_bytes;
+} hr_image;
+
+/* Method parameters.
+ *  bins  : number of levels l (256 or 1024; must be 2^bits)
+ *  iters : T >= 0, the number of Alg. 1 update passes (run exactly T times)
+ *  alpha : weight of the illumination prior of Eq. (10), > 0
+ *  beta  : weight of the reflectance prior of Eq. (10), > 0
+ *  gamma : illumination gamma of Eq. (17), > 0 */
+typedef struct {
+  int32_t bins;
+  int32_t iters;
+  double alpha;
+  double beta;
+  double gamma;
+} hr_params;
+
+/* Launch schedule of the batched form (chosen by the autotuner).
+ *  tile_steps : pixel tile = tile_steps * (256 threads * 16 px (8-bit) or 8 px (10-bit))
+ *  wg_per_cu  : persistent workgroups per compute unit (1..8)
+ *  Zero in a field selects the built-in default. */
+typedef struct {
+  int32_t tile_steps;
+  int32_t wg_per_cu;
+} hr_schedule;
+
+typedef struct hr_workspace hr_workspace;
+
+/* ---- workspace ------------------------------------------------------------ */
+
+/* Create a workspace for up to max_images images per hr_enhance_batch call
+ * at up to max_bins levels (256 or 1024) on the current HIP device.
+ * Allocates device memory; returns HR_ERR_DEVICE if that fails. */
+hr_status hr_workspace_create(int32_t max_images, int32_t max_bins, hr_workspace** ws);
+/* Release a workspace (NULL is ignored).  Synchronises the device first. */
+void hr_workspace_destroy(hr_workspace* ws);
+/* Set the batched-form schedule used by later hr_enhance_batch calls. */
+hr_status hr_workspace_set_schedule(hr_workspace* ws, const hr_schedule* sched);
+/* Read (and clear, if clear != 0) the sticky device flags.  Synchronises the
+ * device. */
+hr_status hr_get_flags(hr_workspace* ws, uint32_t* flags, int32_t clear);
+
+/* ---- the hot path, one image per call -------------------------------------- */
+
+/* Histograms of one image (Eq. 3 and the gradient histogram of Alg. 1).
+ *  hist_v        : device uint32[bins], out: H_C(S), the value-channel histogram
+ *  hist_grad     : device uint32[bins], out: H_C(grad S), the gradient
+ *                  histogram rescaled onto the l levels (sums to width*height)
+ *  hist_grad_raw : device uint32[2*bins-1] or NULL, out: the gradient image's
+ *                  histogram before rescaling (gradient values 0..2(l-1))
+ * The gradient image is |S(x+1,y)-S(x,y)| + |S(x,y+1)-S(x,y)| with the last
+ * column and row replicated; raw level j maps to round-half-up(j(l-1)/gmax),
+ * gmax = largest occupied raw level (all to 0 when gmax = 0). */
+hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
+                        uint32_t* hist_grad_raw, hr_workspace* ws, void* stream);
+
+/* Alg. 1 followed by the reprocessing of Eqs. (17)-(20).
+ *  hist_v, hist_grad : device uint32[bins] (as produced by hr_build_hist)
+ *  npix              : number of pixels N (= sum of hist_v)
+ *  illum             : device float[bins], out: final H~_C(L) of Eq. (14), counts
+ *  refl              : device float[bins], out: final H~_C(R) of Eq. (15), counts
+ *  target            : device float[bins], out: H_C(S~) of Eq. (20), counts
+ * The updates are Eq. (13) for R then Eq. (12) for L (with the weights K of
+ * Eq. (11) multiplying, as in the stationarity conditions of Eq. (10)), then
+ * the rescalings of Eqs. (15), (14), starting from R = H_C(grad S) and
+ * L = H_C(S).  Runs in FP32 on one workgroup. */
+hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix,
+                   const hr_params* p, float* illum, float* refl, float* target, hr_workspace* ws,
+                   void* stream);
+
+/* Histogram matching of the image to `target` (end of Sec. III-C) and the
+ * pixel remap.
+ *  in      : the image the histogram hist_v was built from
+ *  hist_v  : device uint32[bins]
+ *  target  : device float[bins], the target histogram (any positive scale)
+ *  out     : device pointer, same element type and size as `in`, rows
+ *            out_row_stride_bytes apart (may equal in->data)
+ *  lut_out : device uint16[bins] or NULL, out: the level map
+ * LUT[v] = min{k : F~(k) >= (F_S(v-1) + F_S(v))/2}, F~ the normalised running
+ * sum of target and F_S the image CDF; each pixel keeps hue and saturation and
+ * gets value LUT[V]: out_c = round-half-up(c * LUT[V] / V), black -> LUT[0]. */
+hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, const float* target,
+                   void* out, int64_t out_row_stride_bytes, uint16_t* lut_out, hr_workspace* ws,
+                   void* stream);
+
+/* ---- the batched form --------------------------------------------------------- */
+
+/* The whole pipeline (hr_build_hist, hr_solve, hr_match) over n images of
+ * any sizes in one persistent launch, captured once in a HIP graph and
+ * replayed.
+ *  in   : host array [n] of image descriptors (device data pointers)
+ *  out  : host array [n] of device output pointers (same element type/size)
+ *  out_row_stride_bytes : host array [n]
+ *  luts : device uint16[n][bins] or NULL: per-image level maps, out
+ *  illum, refl, target : device float[n][bins] or NULL: per-image solver
+ *         outputs, as hr_solve
+ * n must be in 1..max_images of the workspace. */
+hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes,
+                           int32_t n, int32_t bits, const hr_params* p, uint16_t* luts,
+                           float* illum, float* refl, float* target, hr_workspace* ws,
+                           void* stream);
+
+/* ---- support ------------------------------------------------------------------ */
+
+const char* hr_status_string(hr_status s);
+const char* hr_last_error(void);
+int32_t hr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISTRETINEX_H */

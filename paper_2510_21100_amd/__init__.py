@@ -1,0 +1,16 @@
+"""HistRetinex (arXiv 2510.21100) histogram pipeline on MI355X (gfx950).
+
+The work runs in libhistretinex.so (hand-written HIP, C ABI in
+include/histretinex.h); this package marshals torch tensors into it.
+"""
+
+from .api import (  # noqa: F401
+    Params,
+    Workspace,
+    workspace,
+    build_hist,
+    solve,
+    match,
+    enhance,
+    enhance_batch,
+)

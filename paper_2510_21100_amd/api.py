@@ -1,0 +1,205 @@
+"""Torch-facing API of the HistRetinex library.
+
+Tensors live on the ROCm device; torch provides the memory and the current
+stream, the HIP library does all the work.  Images are (H, W, 3) tensors:
+uint8 for 8-bit (256 levels), uint16 or int16 holding 0..1023 for 10-bit
+(1024 levels).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import HrImage, HrParams, HrSchedule, check, lib
+
+
+@dataclass(frozen=True)
+class Params:
+    """bins l, iterations T, prior weights alpha, beta (Eq. 10), gamma (Eq. 17)."""
+
+    bins: int = 256
+    iters: int = 50
+    alpha: float = 0.01
+    beta: float = 0.01
+    gamma: float = 2.2
+
+    def c(self) -> HrParams:
+        return HrParams(self.bins, self.iters, self.alpha, self.beta, self.gamma)
+
+
+def _bits_of(img: torch.Tensor) -> int:
+    if img.dtype == torch.uint8:
+        return 8
+    if img.dtype in (torch.uint16, torch.int16):
+        return 10
+    raise TypeError("image dtype must be uint8 (8-bit) or uint16/int16 (10-bit)")
+
+
+def _image(img: torch.Tensor) -> HrImage:
+    if img.dim() != 3 or img.shape[2] != 3:
+        raise ValueError("expected an (H, W, 3) image")
+    if not img.is_cuda:
+        raise ValueError("image must be on the GPU")
+    if img.stride(2) != 1 or img.stride(1) != 3:
+        raise ValueError("image pixels must be interleaved RGB (stride (row, 3, 1))")
+    return HrImage(img.data_ptr(), img.shape[1], img.shape[0], img.stride(0) * img.element_size())
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Workspace:
+    """Device scratch, counters and cached launch graphs (one per stream)."""
+
+    def __init__(self, max_images: int = 1, max_bins: int = 1024):
+        h = C.c_void_p()
+        check(lib.hr_workspace_create(max_images, max_bins, C.byref(h)))
+        self.handle = h
+        self.max_images = max_images
+        self.max_bins = max_bins
+
+    def set_schedule(self, tile_steps: int = 0, wg_per_cu: int = 0) -> None:
+        check(lib.hr_workspace_set_schedule(self.handle, C.byref(HrSchedule(tile_steps, wg_per_cu))))
+
+    def flags(self, clear: bool = False) -> int:
+        f = C.c_uint32()
+        check(lib.hr_get_flags(self.handle, C.byref(f), int(clear)))
+        return f.value
+
+    def close(self) -> None:
+        if self.handle:
+            lib.hr_workspace_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ws: dict = {}
+
+
+def workspace(max_images: int = 1, max_bins: int = 1024) -> Workspace:
+    """A process-wide workspace for the current device with room for at least
+    ``max_images`` images."""
+    dev = torch.cuda.current_device()
+    ws = _default_ws.get(dev)
+    if ws is None or ws.max_images < max_images or ws.max_bins < max_bins:
+        if ws is not None:
+            ws.close()
+        ws = Workspace(max(max_images, 1), max(max_bins, 1024))
+        _default_ws[dev] = ws
+    return ws
+
+
+def build_hist(img: torch.Tensor, ws: Workspace | None = None):
+    """Returns (hist_v, hist_grad, hist_grad_raw) as int32 tensors (counts)."""
+    bits = _bits_of(img)
+    bins = 1 << bits
+    ws = ws or workspace()
+    dev = img.device
+    hv = torch.empty(bins, dtype=torch.int32, device=dev)
+    hg = torch.empty(bins, dtype=torch.int32, device=dev)
+    hraw = torch.empty(2 * bins - 1, dtype=torch.int32, device=dev)
+    d = _image(img)
+    check(lib.hr_build_hist(C.byref(d), bits, hv.data_ptr(), hg.data_ptr(), hraw.data_ptr(), ws.handle, _stream()))
+    return hv, hg, hraw
+
+
+def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Params = Params(),
+          ws: Workspace | None = None):
+    """Returns (illum, refl, target) float32 histograms in counts."""
+    ws = ws or workspace()
+    bins = params.bins
+    if hist_v.numel() != bins or hist_grad.numel() != bins:
+        raise ValueError("histograms must have params.bins entries")
+    if hist_v.dtype != torch.int32 or hist_grad.dtype != torch.int32:
+        raise TypeError("histograms must be int32 tensors")
+    dev = hist_v.device
+    illum = torch.empty(bins, dtype=torch.float32, device=dev)
+    refl = torch.empty(bins, dtype=torch.float32, device=dev)
+    target = torch.empty(bins, dtype=torch.float32, device=dev)
+    p = params.c()
+    check(lib.hr_solve(hist_v.contiguous().data_ptr(), hist_grad.contiguous().data_ptr(), int(npix), C.byref(p),
+                       illum.data_ptr(), refl.data_ptr(), target.data_ptr(), ws.handle, _stream()))
+    return illum, refl, target
+
+
+def match(img: torch.Tensor, hist_v: torch.Tensor, target: torch.Tensor, out: torch.Tensor | None = None,
+          ws: Workspace | None = None):
+    """Histogram-match ``img`` to ``target``; returns (out, lut)."""
+    bits = _bits_of(img)
+    bins = 1 << bits
+    ws = ws or workspace()
+    if hist_v.numel() != bins or target.numel() != bins:
+        raise ValueError("histograms must have 2^bits entries")
+    if target.dtype != torch.float32:
+        raise TypeError("target must be float32")
+    if out is None:
+        out = torch.empty_like(img)
+    if out.shape != img.shape or out.dtype != img.dtype:
+        raise ValueError("out must match the image's shape and dtype")
+    lut = torch.empty(bins, dtype=torch.int16, device=img.device)
+    d = _image(img)
+    od = _image(out)
+    check(lib.hr_match(C.byref(d), bits, hist_v.contiguous().data_ptr(), target.contiguous().data_ptr(),
+                       C.c_void_p(od.data), od.row_stride_bytes, lut.data_ptr(), ws.handle, _stream()))
+    return out, lut
+
+
+def enhance(img: torch.Tensor, params: Params | None = None, ws: Workspace | None = None):
+    """One image through the whole pipeline, one launch per stage.
+    Returns (out, extras) with extras = dict of the intermediate histograms."""
+    bits = _bits_of(img)
+    params = params or Params(bins=1 << bits)
+    if params.bins != 1 << bits:
+        raise ValueError("params.bins must equal 2^bits of the image")
+    hv, hg, hraw = build_hist(img, ws)
+    npix = img.shape[0] * img.shape[1]
+    illum, refl, target = solve(hv, hg, npix, params, ws)
+    out, lut = match(img, hv, target, ws=ws)
+    return out, {"hist_v": hv, "hist_grad": hg, "hist_grad_raw": hraw, "illum": illum, "refl": refl,
+                 "target": target, "lut": lut}
+
+
+def enhance_batch(imgs: Sequence[torch.Tensor], params: Params | None = None,
+                  outs: Sequence[torch.Tensor] | None = None, ws: Workspace | None = None,
+                  extras: bool = False):
+    """Many images of any sizes (same bit depth) in one persistent launch.
+    Returns (outs, extras) where extras holds per-image LUTs and solver outputs
+    (stacked (n, bins)) when ``extras`` is set, else None."""
+    n = len(imgs)
+    if n == 0:
+        raise ValueError("empty batch")
+    bits = _bits_of(imgs[0])
+    if any(_bits_of(x) != bits for x in imgs):
+        raise ValueError("all images of a batch must have the same bit depth")
+    bins = 1 << bits
+    params = params or Params(bins=bins)
+    ws = ws or workspace(max_images=n)
+    if outs is None:
+        outs = [torch.empty_like(x) for x in imgs]
+    arr_in = (HrImage * n)(*[_image(x) for x in imgs])
+    arr_out = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    arr_stride = (C.c_int64 * n)(*[o.stride(0) * o.element_size() for o in outs])
+    ex = None
+    ptrs = [None, None, None, None]
+    if extras:
+        dev = imgs[0].device
+        ex = {"lut": torch.empty((n, bins), dtype=torch.int16, device=dev),
+              "illum": torch.empty((n, bins), dtype=torch.float32, device=dev),
+              "refl": torch.empty((n, bins), dtype=torch.float32, device=dev),
+              "target": torch.empty((n, bins), dtype=torch.float32, device=dev)}
+        ptrs = [ex["lut"].data_ptr(), ex["illum"].data_ptr(), ex["refl"].data_ptr(), ex["target"].data_ptr()]
+    p = params.c()
+    check(lib.hr_enhance_batch(arr_in, arr_out, arr_stride, n, bits, C.byref(p), ptrs[0], ptrs[1], ptrs[2],
+                               ptrs[3], ws.handle, _stream()))
+    return list(outs), ex

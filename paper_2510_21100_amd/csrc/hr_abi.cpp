@@ -1,0 +1,384 @@
+// C ABI of the HistRetinex library: argument validation, the workspace,
+// kernel launches and the captured launch graph of the batched form.
+// Validation happens before anything is enqueued; HIP errors become
+// HR_ERR_DEVICE with the runtime's text in hr_last_error().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/histretinex.h"
+#include "hr_launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+hr_status fail(hr_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HR_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(HR_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kPlainTileSteps = 16;
+constexpr int kDefaultTileSteps = 16;
+constexpr int kDefaultWgPerCu = 2;
+constexpr int kStaging = 2;
+
+size_t table_bytes(int max_images) {
+  return sizeof(hr::BatchHeader) + (size_t)max_images * sizeof(hr::ImgDesc);
+}
+
+struct GraphEntry {
+  bool valid = false;
+  int bits = 0;
+  int grid = 0;
+  hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct hr_workspace {
+  int device = 0;
+  int max_images = 0;
+  int max_bins = 0;
+  int cu_count = 0;
+  hr_schedule sched{kDefaultTileSteps, kDefaultWgPerCu};
+  uint32_t* d_flags = nullptr;   // [0] sticky flags, [1] plain-hist ticket
+  uint32_t* d_graw = nullptr;    // plain: raw gradient histogram scratch [2*max_bins]
+  uint16_t* d_lut = nullptr;     // plain: LUT scratch [max_bins]
+  uint32_t* d_lists = nullptr;   // per image: 3 * bins^2 words of solver lists
+  int64_t lists_words = 0;       // words per image slot
+  uint8_t* d_table = nullptr;    // BatchHeader + ImgDesc[max_images]
+  uint32_t* d_state = nullptr;   // ImageState per image
+  uint8_t* h_stage[kStaging] = {nullptr, nullptr};
+  hipEvent_t ev[kStaging] = {nullptr, nullptr};
+  bool ev_used[kStaging] = {false, false};
+  int slot = 0;
+  hipStream_t capture = nullptr;
+  GraphEntry graphs[kStaging][2];
+};
+
+namespace {
+
+int elem_size(int bits) { return bits == 8 ? 1 : 2; }
+
+hr_status check_bits(int32_t bits) {
+  if (bits != 8 && bits != 10) return fail(HR_ERR_UNSUPPORTED, "bits must be 8 or 10");
+  return HR_OK;
+}
+
+hr_status check_ws(hr_workspace* ws, int bins) {
+  if (!ws) return fail(HR_ERR_INVALID_ARG, "workspace is NULL");
+  if (bins > ws->max_bins) return fail(HR_ERR_WORKSPACE, "workspace was created for fewer bins");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ws->device)
+    return fail(HR_ERR_INVALID_ARG, "current HIP device differs from the workspace's device");
+  return HR_OK;
+}
+
+// Validates one image and fills the kernel descriptor (in part).
+hr_status make_desc(const hr_image* img, int bits, const char* what, hr::ImgDesc* d) {
+  if (!img) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": image descriptor is NULL");
+  if (!img->data) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": image data is NULL");
+  if (img->width <= 0 || img->height <= 0)
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": width and height must be positive");
+  if (img->width > hr::launch::max_width(bits))
+    return fail(HR_ERR_UNSUPPORTED, std::string(what) + ": image wider than " +
+                                        std::to_string(hr::launch::max_width(bits)) + " pixels");
+  const int es = elem_size(bits);
+  const int64_t row = 3LL * img->width * es;
+  if (img->row_stride_bytes < row)
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": row stride smaller than 3 * width * element size");
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(img->data);
+  if (es == 2 && ((addr & 1u) || (img->row_stride_bytes & 1)))
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": 16-bit image data and stride must be even");
+  const int64_t npix = (int64_t)img->width * img->height;
+  if (npix >= (1LL << 32) - 1) return fail(HR_ERR_UNSUPPORTED, std::string(what) + ": image has 2^32 or more pixels");
+  std::memset(d, 0, sizeof(*d));
+  d->in = static_cast<const uint8_t*>(img->data);
+  d->in_stride = img->row_stride_bytes;
+  d->npix = npix;
+  d->W = img->width;
+  d->H = img->height;
+  d->in_vec = (img->row_stride_bytes == row) && ((addr & 15u) == 0);
+  return HR_OK;
+}
+
+hr_status set_out(hr::ImgDesc* d, void* out, int64_t stride, int bits, const char* what) {
+  if (!out) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": output pointer is NULL");
+  const int64_t row = 3LL * d->W * elem_size(bits);
+  if (stride < row) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": output row stride too small");
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(out);
+  if (elem_size(bits) == 2 && ((addr & 1u) || (stride & 1)))
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": 16-bit output data and stride must be even");
+  d->out = static_cast<uint8_t*>(out);
+  d->out_stride = stride;
+  d->out_vec = (stride == row) && ((addr & 15u) == 0);
+  return HR_OK;
+}
+
+hr_status check_params(const hr_params* p, int bits) {
+  if (!p) return fail(HR_ERR_INVALID_ARG, "params is NULL");
+  if (p->bins != 256 && p->bins != 1024) return fail(HR_ERR_UNSUPPORTED, "bins must be 256 or 1024");
+  if (bits && p->bins != (1 << bits)) return fail(HR_ERR_INVALID_ARG, "bins must equal 2^bits");
+  if (p->iters < 0 || p->iters > 100000) return fail(HR_ERR_INVALID_ARG, "iters must be in 0..100000");
+  if (!(std::isfinite(p->alpha) && p->alpha > 0)) return fail(HR_ERR_INVALID_ARG, "alpha must be finite and > 0");
+  if (!(std::isfinite(p->beta) && p->beta > 0)) return fail(HR_ERR_INVALID_ARG, "beta must be finite and > 0");
+  if (!(std::isfinite(p->gamma) && p->gamma > 0)) return fail(HR_ERR_INVALID_ARG, "gamma must be finite and > 0");
+  return HR_OK;
+}
+
+hr::SolveParams solve_params(const hr_params* p) {
+  hr::SolveParams sp{};
+  sp.iters = p->iters;
+  sp.alpha = (float)p->alpha;
+  sp.beta = (float)p->beta;
+  sp.inv_gamma = 1.0 / p->gamma;
+  return sp;
+}
+
+void release(hr_workspace* ws) {
+  if (!ws) return;
+  for (int s = 0; s < kStaging; ++s) {
+    for (int b = 0; b < 2; ++b)
+      if (ws->graphs[s][b].exec) (void)hipGraphExecDestroy(ws->graphs[s][b].exec);
+    if (ws->ev[s]) (void)hipEventDestroy(ws->ev[s]);
+    if (ws->h_stage[s]) (void)hipHostFree(ws->h_stage[s]);
+  }
+  if (ws->capture) (void)hipStreamDestroy(ws->capture);
+  (void)hipFree(ws->d_flags);
+  (void)hipFree(ws->d_graw);
+  (void)hipFree(ws->d_lut);
+  (void)hipFree(ws->d_lists);
+  (void)hipFree(ws->d_table);
+  (void)hipFree(ws->d_state);
+  delete ws;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hr_abi_version(void) { return HR_ABI_VERSION; }
+
+const char* hr_last_error(void) { return g_err.c_str(); }
+
+const char* hr_status_string(hr_status s) {
+  switch (s) {
+    case HR_OK: return "ok";
+    case HR_ERR_INVALID_ARG: return "invalid argument";
+    case HR_ERR_UNSUPPORTED: return "unsupported";
+    case HR_ERR_WORKSPACE: return "workspace too small";
+    case HR_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+hr_status hr_workspace_create(int32_t max_images, int32_t max_bins, hr_workspace** out) {
+  if (!out) return fail(HR_ERR_INVALID_ARG, "output pointer is NULL");
+  *out = nullptr;
+  if (max_images < 1 || max_images > 65536) return fail(HR_ERR_INVALID_ARG, "max_images must be in 1..65536");
+  if (max_bins != 256 && max_bins != 1024) return fail(HR_ERR_UNSUPPORTED, "max_bins must be 256 or 1024");
+  hr_workspace* ws = new (std::nothrow) hr_workspace();
+  if (!ws) return fail(HR_ERR_DEVICE, "host allocation failed");
+  ws->max_images = max_images;
+  ws->max_bins = max_bins;
+#define HR_HIP_WS(call)                                                                           \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) {                                                                       \
+      release(ws);                                                                                \
+      return fail(HR_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));              \
+    }                                                                                             \
+  } while (0)
+  HR_HIP_WS(hipGetDevice(&ws->device));
+  HR_HIP_WS(hipDeviceGetAttribute(&ws->cu_count, hipDeviceAttributeMultiprocessorCount, ws->device));
+  HR_HIP_WS(hipMalloc(&ws->d_flags, 64));
+  HR_HIP_WS(hipMalloc(&ws->d_graw, sizeof(uint32_t) * 2 * max_bins));
+  HR_HIP_WS(hipMalloc(&ws->d_lut, sizeof(uint16_t) * max_bins));
+  ws->lists_words = 3LL * max_bins * max_bins;
+  HR_HIP_WS(hipMalloc(&ws->d_lists, sizeof(uint32_t) * ws->lists_words * max_images));
+  HR_HIP_WS(hipMalloc(&ws->d_table, table_bytes(max_images)));
+  HR_HIP_WS(hipMalloc(&ws->d_state, sizeof(uint32_t) * hr::ImageState::words(max_bins) * max_images));
+  for (int s = 0; s < kStaging; ++s) {
+    HR_HIP_WS(hipHostMalloc(&ws->h_stage[s], table_bytes(max_images), hipHostMallocDefault));
+    std::memset(ws->h_stage[s], 0, table_bytes(max_images));
+    HR_HIP_WS(hipEventCreateWithFlags(&ws->ev[s], hipEventDisableTiming));
+  }
+  HR_HIP_WS(hipStreamCreateWithFlags(&ws->capture, hipStreamNonBlocking));
+  HR_HIP_WS(hipMemset(ws->d_flags, 0, 64));
+  HR_HIP_WS(hipMemset(ws->d_state, 0, sizeof(uint32_t) * hr::ImageState::words(max_bins) * max_images));
+  HR_HIP_WS(hipDeviceSynchronize());
+#undef HR_HIP_WS
+  *out = ws;
+  return HR_OK;
+}
+
+void hr_workspace_destroy(hr_workspace* ws) {
+  if (!ws) return;
+  (void)hipDeviceSynchronize();
+  release(ws);
+}
+
+hr_status hr_workspace_set_schedule(hr_workspace* ws, const hr_schedule* sched) {
+  if (!ws || !sched) return fail(HR_ERR_INVALID_ARG, "NULL argument");
+  if (sched->tile_steps < 0 || sched->tile_steps > 4096) return fail(HR_ERR_INVALID_ARG, "tile_steps out of range");
+  if (sched->wg_per_cu < 0 || sched->wg_per_cu > 8) return fail(HR_ERR_INVALID_ARG, "wg_per_cu out of range");
+  ws->sched.tile_steps = sched->tile_steps ? sched->tile_steps : kDefaultTileSteps;
+  ws->sched.wg_per_cu = sched->wg_per_cu ? sched->wg_per_cu : kDefaultWgPerCu;
+  return HR_OK;
+}
+
+hr_status hr_get_flags(hr_workspace* ws, uint32_t* flags, int32_t clear) {
+  if (!ws || !flags) return fail(HR_ERR_INVALID_ARG, "NULL argument");
+  HR_HIP(hipDeviceSynchronize());
+  HR_HIP(hipMemcpy(flags, ws->d_flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (clear) HR_HIP(hipMemset(ws->d_flags, 0, sizeof(uint32_t)));
+  return HR_OK;
+}
+
+hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
+                        uint32_t* hist_grad_raw, hr_workspace* ws, void* stream) {
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  const int bins = 1 << bits;
+  hr::ImgDesc d;
+  if ((st = make_desc(img, bits, "hr_build_hist", &d))) return st;
+  if (!hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_build_hist: histogram pointer is NULL");
+  if ((st = check_ws(ws, bins))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* graw = hist_grad_raw ? hist_grad_raw : ws->d_graw;
+  HR_HIP(hr::launch::fill_u32(hist_v, bins, 0, s));
+  HR_HIP(hr::launch::fill_u32(graw, 2 * bins - 1, 0, s));
+  const int64_t tile_px = (int64_t)kPlainTileSteps * hr::launch::step_px(bits);
+  HR_HIP(hr::launch::hist(bits, d, tile_px, hist_v, graw, hist_grad, ws->d_flags + 1, ws->d_flags, s));
+  return HR_OK;
+}
+
+hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix, const hr_params* p,
+                   float* illum, float* refl, float* target, hr_workspace* ws, void* stream) {
+  hr_status st = check_params(p, 0);
+  if (st) return st;
+  if (!hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_solve: histogram pointer is NULL");
+  if (!illum || !refl || !target) return fail(HR_ERR_INVALID_ARG, "hr_solve: output pointer is NULL");
+  if (npix <= 0 || npix >= (1LL << 32) - 1) return fail(HR_ERR_INVALID_ARG, "hr_solve: npix out of range");
+  if ((st = check_ws(ws, p->bins))) return st;
+  const hr::SolveParams sp = solve_params(p);
+  HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, ws->d_lists, illum, refl, target, ws->d_flags,
+                           static_cast<hipStream_t>(stream)));
+  return HR_OK;
+}
+
+hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, const float* target, void* out,
+                   int64_t out_row_stride_bytes, uint16_t* lut_out, hr_workspace* ws, void* stream) {
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  const int bins = 1 << bits;
+  hr::ImgDesc d;
+  if ((st = make_desc(in, bits, "hr_match", &d))) return st;
+  if ((st = set_out(&d, out, out_row_stride_bytes, bits, "hr_match"))) return st;
+  if (!hist_v || !target) return fail(HR_ERR_INVALID_ARG, "hr_match: histogram pointer is NULL");
+  if ((st = check_ws(ws, bins))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HR_HIP(hr::launch::lut(bins, hist_v, target, ws->d_lut, lut_out, s));
+  const int64_t tile_px = (int64_t)kPlainTileSteps * hr::launch::step_px(bits);
+  HR_HIP(hr::launch::remap(bits, d, tile_px, ws->d_lut, s));
+  return HR_OK;
+}
+
+hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes, int32_t n,
+                           int32_t bits, const hr_params* p, uint16_t* luts, float* illum, float* refl,
+                           float* target, hr_workspace* ws, void* stream) {
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  if ((st = check_params(p, bits))) return st;
+  const int bins = 1 << bits;
+  if (!in || !out || !out_row_stride_bytes) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch: NULL array");
+  if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch: n must be >= 1");
+  std::vector<hr::ImgDesc> descs((size_t)n);
+  for (int i = 0; i < n; ++i) {
+    if ((st = make_desc(&in[i], bits, "hr_enhance_batch", &descs[i]))) return st;
+    if ((st = set_out(&descs[i], out[i], out_row_stride_bytes[i], bits, "hr_enhance_batch"))) return st;
+    descs[i].slot = i;
+  }
+  if ((st = check_ws(ws, bins))) return st;
+  if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_enhance_batch: n exceeds the workspace's max_images");
+  // largest image first, so the last solves to start belong to small images
+  std::vector<int> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return descs[a].npix > descs[b].npix; });
+  const int64_t tile_px = (int64_t)ws->sched.tile_steps * hr::launch::step_px(bits);
+  int64_t tiles = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int slot = ws->slot;
+  if (ws->ev_used[slot]) HR_HIP(hipEventSynchronize(ws->ev[slot]));
+  uint8_t* stage = ws->h_stage[slot];
+  hr::ImgDesc* sd = reinterpret_cast<hr::ImgDesc*>(stage + sizeof(hr::BatchHeader));
+  for (int k = 0; k < n; ++k) {
+    hr::ImgDesc d = descs[order[k]];
+    d.ntiles = (int32_t)((d.npix + tile_px - 1) / tile_px);
+    d.tile0 = (int32_t)tiles;
+    tiles += d.ntiles;
+    if (tiles > (1LL << 30)) return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch: too many tiles");
+    sd[k] = d;
+  }
+  hr::BatchHeader hdr{};
+  hdr.n = n;
+  hdr.total_tiles = (int32_t)tiles;
+  hdr.tile_px = tile_px;
+  hdr.params = solve_params(p);
+  hdr.out = hr::BatchOut{luts, illum, refl, target};
+  std::memcpy(stage, &hdr, sizeof(hdr));
+
+  const int grid = std::max(1, ws->cu_count * ws->sched.wg_per_cu);
+  GraphEntry& g = ws->graphs[slot][bits == 8 ? 0 : 1];
+  if (!g.valid || g.grid != grid) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+      g.valid = false;
+    }
+    auto* hdr_d = reinterpret_cast<hr::BatchHeader*>(ws->d_table);
+    auto* desc_d = reinterpret_cast<hr::ImgDesc*>(ws->d_table + sizeof(hr::BatchHeader));
+    auto* st_d = reinterpret_cast<hr::ImageState*>(ws->d_state);
+    hipGraph_t graph = nullptr;
+    HR_HIP(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = hipMemcpyAsync(ws->d_table, stage, table_bytes(ws->max_images), hipMemcpyHostToDevice, ws->capture);
+    hipError_t e2 = e1 == hipSuccess ? hr::launch::batch_reset(hdr_d, st_d, bins, ws->capture) : e1;
+    hipError_t e3 = e2 == hipSuccess ? hr::launch::batch(bits, grid, hdr_d, desc_d, st_d, ws->d_lists,
+                                                        3LL * bins * bins, ws->d_flags, ws->capture)
+                                     : e2;
+    hipError_t e4 = hipStreamEndCapture(ws->capture, &graph);
+    if (e3 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(HR_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e3));
+    }
+    if (e4 != hipSuccess) return fail(HR_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e4));
+    hipError_t e5 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e5 != hipSuccess) return fail(HR_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e5));
+    g.valid = true;
+    g.bits = bits;
+    g.grid = grid;
+  }
+  HR_HIP(hipGraphLaunch(g.exec, s));
+  HR_HIP(hipEventRecord(ws->ev[slot], s));
+  ws->ev_used[slot] = true;
+  ws->slot = (slot + 1) % kStaging;
+  return HR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Declarations shared by the kernels and the C-ABI host layer: the batched
+// form's device-side tables and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hr {
+
+// One image as the kernels see it.  Pixel p (flat, row-major) is at
+// in + (p / W) * in_stride + 3 * (p % W) * sizeof(pix_t).
+struct ImgDesc {
+  const uint8_t* in;
+  uint8_t* out;
+  int64_t in_stride;
+  int64_t out_stride;
+  int64_t npix;
+  int32_t W;
+  int32_t H;
+  int32_t in_vec;   // rows are tight and the base is 16-byte aligned
+  int32_t out_vec;
+  int32_t ntiles;   // batched form: number of pixel tiles of this image
+  int32_t tile0;    // batched form: first tile of this image in the batch
+  int32_t slot;     // batched form: index of this image in the caller's arrays
+  int32_t pad;
+};
+
+// Solver parameters as the kernels take them.
+struct SolveParams {
+  int32_t iters;
+  float alpha;
+  float beta;
+  int32_t pad;
+  double inv_gamma;
+};
+
+// Optional per-image outputs of the batched form, indexed by the caller's slot.
+struct BatchOut {
+  uint16_t* luts;
+  float* illum;
+  float* refl;
+  float* target;
+};
+
+// Header of the batched descriptor table (device copy written per call, so a
+// captured launch graph serves every call).
+struct BatchHeader {
+  uint32_t next;         // work-queue cursor (reset on the device each call)
+  uint32_t pad0;
+  int32_t n;             // images in this call
+  int32_t total_tiles;   // histogram tiles (= remap tiles) over all images
+  int64_t tile_px;       // pixels per tile (multiple of the pixel step)
+  SolveParams params;
+  BatchOut out;
+};
+
+// Per-image device state of the batched form, `words(bins)` 32-bit words.
+struct ImageState {
+  uint32_t done;   // histogram tiles merged so far
+  uint32_t ready;  // LUT published
+  uint32_t pad[2];
+  static constexpr int64_t words(int bins) { return 4 + 5 * (int64_t)bins + bins / 2; }
+  __host__ __device__ uint32_t* base() { return reinterpret_cast<uint32_t*>(this); }
+  __host__ __device__ uint32_t* hs() { return base() + 4; }
+  __host__ __device__ uint32_t* graw(int bins) { return base() + 4 + bins; }
+  __host__ __device__ uint32_t* hg(int bins) { return base() + 4 + 3 * bins; }
+  __host__ __device__ float* target(int bins) { return reinterpret_cast<float*>(base() + 4 + 4 * bins); }
+  __host__ __device__ uint16_t* lut(int bins) { return reinterpret_cast<uint16_t*>(base() + 4 + 5 * bins); }
+};
+
+namespace launch {
+hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint32_t* graw, uint32_t* hg,
+                uint32_t* ticket, uint32_t* flags, hipStream_t s);
+hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
+                 uint32_t* lists, float* illum, float* refl, float* target, uint32_t* flags, hipStream_t s);
+hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut, uint16_t* lut_user,
+               hipStream_t s);
+hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lut, hipStream_t s);
+hipError_t batch_reset(BatchHeader* hdr, ImageState* st, int bins, hipStream_t s);
+hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImageState* st, uint32_t* lists,
+                 int64_t lists_stride, uint32_t* flags, hipStream_t s);
+int step_px(int bits);
+int max_width(int bits);
+}  // namespace launch
+
+}  // namespace hr

@@ -1,0 +1,138 @@
+"""The batched persistent form against the one-image form and the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synthetic import config_seed, make_batch_shapes, make_image
+from gpu_cases import lut_contract, padded_gpu, pixel_contract, rel_err, to_gpu, to_np, REL_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_2510_21100_amd as H
+    assert torch.cuda.is_available()
+    return H
+
+
+def _batch_imgs(shapes, bits=8, cfg=3):
+    n = len(shapes)
+    rng = np.random.default_rng(11)
+    return [make_image(config_seed(cfg, n, i), h, w, bits=bits, ceil=float(rng.uniform(0.03, 0.4)))
+            for i, (h, w) in enumerate(shapes)]
+
+
+def _compare_to_plain(H, imgs, gimgs, params, ws=None):
+    outs, ex = H.enhance_batch(gimgs, params, extras=True, ws=ws)
+    torch.cuda.synchronize()
+    for i, g in enumerate(gimgs):
+        out_p, exp = H.enhance(g, params)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i], out_p), i
+        assert torch.equal(ex["lut"][i], exp["lut"]), i
+        assert torch.equal(ex["illum"][i], exp["illum"]), i
+        assert torch.equal(ex["refl"][i], exp["refl"]), i
+        assert torch.equal(ex["target"][i], exp["target"]), i
+    return outs, ex
+
+
+SHAPES = [(480, 640), (97, 1201), (1, 333), (300, 77), (13, 13), (664, 1000), (2000, 37)]
+
+
+def test_batch_equals_plain_8bit(H):
+    imgs = _batch_imgs(SHAPES)
+    _compare_to_plain(H, imgs, [to_gpu(x) for x in imgs], H.Params(bins=256))
+
+
+def test_batch_equals_plain_10bit(H):
+    shapes = [(216, 384), (61, 700), (400, 33)]
+    imgs = _batch_imgs(shapes, bits=10, cfg=4)
+    _compare_to_plain(H, imgs, [to_gpu(x) for x in imgs], H.Params(bins=1024))
+
+
+def test_batch_graph_replay_changing_batches(H):
+    """Consecutive calls replay the captured graph with new descriptors;
+    every replay must equal the one-image path."""
+    ws = H.Workspace(max_images=8, max_bins=256)
+    for rep, shapes in enumerate([SHAPES[:3], SHAPES[2:7], SHAPES[:3], [(50, 60)]]):
+        imgs = _batch_imgs(shapes)
+        gimgs = [to_gpu(x) for x in imgs]
+        if rep == 1:
+            gimgs[1] = padded_gpu(imgs[1], 3, 1)  # strided member
+        _compare_to_plain(H, imgs, gimgs, H.Params(bins=256), ws=ws)
+    ws.close()
+
+
+def test_batch_schedules_agree(H):
+    imgs = _batch_imgs(SHAPES[:5])
+    gimgs = [to_gpu(x) for x in imgs]
+    ref, _ = H.enhance_batch(gimgs, H.Params(bins=256))
+    torch.cuda.synchronize()
+    ws = H.Workspace(max_images=8, max_bins=256)
+    for ts, wg in [(1, 1), (4, 3), (64, 2), (16, 4)]:
+        ws.set_schedule(ts, wg)
+        outs, _ = H.enhance_batch(gimgs, H.Params(bins=256), ws=ws)
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), (ts, wg)
+    ws.close()
+
+
+def test_batch_vs_oracle(H):
+    imgs = _batch_imgs([(300, 400), (128, 999)])
+    outs, ex = H.enhance_batch([to_gpu(x) for x in imgs], H.Params(bins=256), extras=True)
+    torch.cuda.synchronize()
+    for i, img in enumerate(imgs):
+        ref = O.enhance(img, O.Params(bins=256))
+        assert rel_err(to_np(ex["illum"][i]), ref["illum"]) <= REL_TOL
+        lut_contract(to_np(ex["lut"][i]), ref)
+        pixel_contract(to_np(outs[i]), ref["out"])
+
+
+def test_clamped_10bit_values_flag(H):
+    img = make_image(config_seed(4, 1, 0), 40, 64, bits=10)
+    bad = img.copy()
+    bad[3, 5, 1] = 1500
+    bad[10, 60, 2] = 65535
+    ws = H.Workspace(max_images=2, max_bins=1024)
+    ws.flags(clear=True)
+    out, ex = H.enhance(to_gpu(bad), H.Params(bins=1024), ws=ws)
+    torch.cuda.synchronize()
+    assert ws.flags(clear=True) & 1
+    ref = O.enhance(np.minimum(bad, 1023), O.Params(bins=1024))
+    assert np.array_equal(to_np(ex["hist_v"]).astype(np.int64), ref["hS"])
+    outs, _ = H.enhance_batch([to_gpu(bad)], H.Params(bins=1024), ws=ws)
+    torch.cuda.synchronize()
+    assert ws.flags(clear=True) & 1
+    assert torch.equal(outs[0], out)
+    ws.close()
+
+
+def test_full_size_ragged_batch_sampled(H):
+    """The benchmark's 64-image ragged batch: every image's value channel after
+    remap equals its LUT (exact property at any size), and three sampled
+    images match the oracle in full."""
+    shapes = make_batch_shapes(config_seed(3, 1, 0), 64)
+    n = len(shapes)
+    rng = np.random.default_rng(2510211003)
+    ceils = rng.uniform(0.03, 0.4, size=n)
+    sample = {0, 31, 63}
+    gimgs, kept = [], {}
+    for i, (h, w) in enumerate(shapes):
+        img = make_image(config_seed(3, n, i), h, w, ceil=float(ceils[i]))
+        if i in sample:
+            kept[i] = img
+        gimgs.append(to_gpu(img))
+    outs, ex = H.enhance_batch(gimgs, H.Params(bins=256), extras=True)
+    torch.cuda.synchronize()
+    for i, (g, o) in enumerate(zip(gimgs, outs)):
+        v = g.max(dim=2).values.long()
+        lut = ex["lut"][i].long()
+        assert torch.equal(o.max(dim=2).values.long(), lut[v]), i
+    for i, img in kept.items():
+        ref = O.enhance(img, O.Params(bins=256))
+        lut_contract(to_np(ex["lut"][i]), ref)
+        pixel_contract(to_np(outs[i]), ref["out"])
