@@ -1,0 +1,249 @@
+"""Benchmark of the HistRetinex histogram pipeline on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged64|uhd16]
+
+A step is one pass of the whole pipeline (histograms, solver, target, LUT,
+remap) over one batch of synthetic low-light images that are already resident
+in HBM.  The timed form is the batched persistent launch; the one-image form
+(one launch sequence per image) is timed on the same batch for the
+batched-vs-plain ratio.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from synthetic import config_seed, make_batch_shapes, make_image  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "Mpix/s end-to-end enhancement (batched vs plain, 1 GPU) + % HBM roofline"
+
+
+def _gen(args):
+    cfg, n, i, h, w, bits, ceil = args
+    return make_image(config_seed(cfg, n, i), h, w, bits=bits, ceil=ceil)
+
+
+def workload(name: str):
+    """(description, bits, list of generator jobs)."""
+    if name == "ragged64":
+        n = 64
+        shapes = make_batch_shapes(config_seed(3, 1, 0), n)
+        rng = np.random.default_rng(2510211003)
+        ceils = rng.uniform(0.03, 0.4, size=n)
+        jobs = [(3, n, i, h, w, 8, float(ceils[i])) for i, (h, w) in enumerate(shapes)]
+        desc = ("64 RGB uint8 images, W~U{640..4000}, H~U{480..3000}, illumination ceiling U[0.03,0.4], "
+                "256 bins, 50 iterations")
+        return desc, 8, jobs
+    if name == "uhd16":
+        n = 16
+        shapes = [(2160, 3840) if i % 2 == 0 else (4320, 7680) for i in range(n)]
+        jobs = [(4, n, i, h, w, 10, 0.3) for i, (h, w) in enumerate(shapes)]
+        desc = "8 x 3840x2160 + 8 x 7680x4320 RGB uint16 10-bit images, 1024 bins, 50 iterations"
+        return desc, 10, jobs
+    if name == "single":
+        jobs = [(2, 1, 0, 664, 1000, 8, 0.3)]
+        return "one 1000x664 RGB uint8 image, 256 bins, 50 iterations", 8, jobs
+    raise SystemExit(f"unknown workload {name}")
+
+
+def generate(jobs, workers: int):
+    if len(jobs) == 1 or workers <= 1:
+        return [_gen(j) for j in jobs]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_gen, jobs))
+
+
+def cpu_baseline(imgs, bits, budget_s: float):
+    """The FP64 oracle, as it is, on whole images of the workload until about
+    budget_s seconds of CPU time have been spent (at least one image)."""
+    import oracle as O
+
+    params = O.Params(bins=1 << bits, iters=50)
+    O.classify(params.bins)  # one-time table, not timed
+    O.classify_enhanced(params.bins, params.gamma)
+    order = sorted(range(len(imgs)), key=lambda i: imgs[i].shape[0] * imgs[i].shape[1])
+    done_px, spent, used = 0, 0.0, []
+    for i in order:
+        t0 = time.perf_counter()
+        O.enhance(imgs[i], params)
+        spent += time.perf_counter() - t0
+        done_px += imgs[i].shape[0] * imgs[i].shape[1]
+        used.append(i)
+        if spent >= budget_s:
+            break
+    return {
+        "value": done_px / spent / 1e6,
+        "unit": "Mpix/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(used)} whole image(s) of the workload, smallest first, {done_px} pixels, "
+                  f"{spent:.1f} s, single-threaded numpy FP64",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--workload", default="ragged64", choices=["ragged64", "uhd16", "single"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--tile-steps", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--remap-steps", type=int, default=0)
+    ap.add_argument("--schedule", default=os.path.join(ROOT, "paper_2510_21100_amd", "schedule.json"))
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the images of a batch are independent and this build "
+              "measures one GPU's share; use --gpus 1", file=sys.stderr)
+        raise SystemExit(2)
+
+    desc, bits, jobs = workload(args.workload)
+    t0 = time.perf_counter()
+    imgs = generate(jobs, args.workers)
+    gen_s = time.perf_counter() - t0
+
+    import torch
+
+    import paper_2510_21100_amd as H
+    from paper_2510_21100_amd import tune
+
+    bins = 1 << bits
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    def to_dev(x):
+        t = torch.from_numpy(x)
+        if t.dtype == torch.uint16:
+            t = t.view(torch.int16)
+        return t.to(dev)
+
+    gimgs = [to_dev(x) for x in imgs]
+    outs = [torch.empty_like(g) for g in gimgs]
+    npix = sum(g.shape[0] * g.shape[1] for g in gimgs)
+    esz = 1 if bits == 8 else 2
+    alg_bytes = 9 * esz * npix  # read + re-read + write of 3 channels
+    params = H.Params(bins=bins, iters=50)
+    ws = H.Workspace(max_images=len(gimgs), max_bins=bins)
+    sched = (args.tile_steps, args.wg_per_cu, args.remap_steps)
+    if sched == (0, 0, 0):
+        sched = tune.lookup(args.schedule, bins, esz, npix, len(gimgs)) or (0, 0, 0)
+    ws.set_schedule(*sched)
+    stream = torch.cuda.current_stream()
+
+    # ---- batched form --------------------------------------------------------
+    for _ in range(args.warmup):
+        H.enhance_batch(gimgs, params, outs=outs, ws=ws)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        H.enhance_batch(gimgs, params, outs=outs, ws=ws)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_step = wall * 1e3 / args.steps
+    value = npix / (ms_step * 1e-3) / 1e6
+    avg_launch_s = float(np.mean(launch_ms)) * 1e-3
+    achieved = alg_bytes / avg_launch_s / 1e9
+
+    # ---- one-image form on the same batch -------------------------------------
+    pl_ws = H.Workspace(max_images=1, max_bins=bins)
+    pouts = outs
+    for _ in range(1):
+        for g, o in zip(gimgs, pouts):
+            hv, hg, _ = H.build_hist(g, pl_ws)
+            _, _, tg = H.solve(hv, hg, g.shape[0] * g.shape[1], params, pl_ws)
+            H.match(g, hv, tg, out=o, ws=pl_ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        for g, o in zip(gimgs, pouts):
+            hv, hg, _ = H.build_hist(g, pl_ws)
+            _, _, tg = H.solve(hv, hg, g.shape[0] * g.shape[1], params, pl_ws)
+            H.match(g, hv, tg, out=o, ws=pl_ws)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t1) * 1e3 / args.plain_steps
+    plain_value = npix / (plain_ms * 1e-3) / 1e6
+
+    # ---- solver alone (one image's histograms) ------------------------------
+    hv, hg, _ = H.build_hist(gimgs[0], pl_ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        H.solve(hv, hg, gimgs[0].shape[0] * gimgs[0].shape[1], params, pl_ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    solve_us = e0.elapsed_time(e1) * 1e3 / reps
+
+    cpu = None
+    if args.cpu_budget > 0:
+        cpu = cpu_baseline(imgs, bits, args.cpu_budget)
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if bits == 8 else "u16",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "form": "batched: one persistent launch per step, replayed from a captured HIP graph",
+            "images": len(gimgs),
+            "pixels": npix,
+            "bins": bins,
+            "iters": 50,
+            "schedule": {"tile_steps": sched[0], "wg_per_cu": sched[1], "remap_steps": sched[2]},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None,
+            "kernel": f"k_batch<{bits}> (graph: descriptor copy + state reset + persistent kernel)",
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+        },
+        "plain": {"value": round(plain_value, 1), "unit": "Mpix/s", "ms_per_step": round(plain_ms, 3),
+                  "batched_over_plain": round(value / plain_value, 3)},
+        "solve_us_per_image": round(solve_us, 1),
+        "gen_seconds": round(gen_s, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ws.close()
+    pl_ws.close()
+
+
+if __name__ == "__main__":
+    main()

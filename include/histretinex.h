@@ -15,7 +15,7 @@
  *    (bits = 10, 1024 levels).  Rows are row_stride_bytes apart; a stride of
  *    exactly 3*width*element_size with a 16-byte aligned base takes the
  *    vectorised path, any other stride >= that takes a slower scalar path.
- *  - Widths up to 24576 (8-bit) / 12288 (10-bit) are supported.
+ *  - Widths up to 16384 (8-bit) / 8192 (10-bit) are supported.
  *  - bins must equal 2^bits.
  *  - All device pointers are caller-owned; the library never frees them.
  *  - Every compute call is asynchronous and ordered on `stream` (a
@@ -78,13 +78,17 @@ typedef struct {
   double gamma;
 } hr_params;
 
-/* Launch schedule of the batched form (chosen by the autotuner).
- *  tile_steps : pixel tile = tile_steps * (256 threads * 16 px (8-bit) or 8 px (10-bit))
- *  wg_per_cu  : persistent workgroups per compute unit (1..8)
+/* Launch schedule of the batched form (chosen by the autotuner).  A step is
+ * one pass of the persistent workgroup over its pixels: 512 threads x 16 px
+ * (8-bit) or x 8 px (10-bit).
+ *  tile_steps  : steps per histogram work item
+ *  wg_per_cu   : persistent workgroups per compute unit (1..8)
+ *  remap_steps : steps per remap work item
  *  Zero in a field selects the built-in default. */
 typedef struct {
   int32_t tile_steps;
   int32_t wg_per_cu;
+  int32_t remap_steps;
 } hr_schedule;
 
 typedef struct hr_workspace hr_workspace;

@@ -40,7 +40,7 @@ class HrParams(C.Structure):
 
 
 class HrSchedule(C.Structure):
-    _fields_ = [("tile_steps", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("tile_steps", C.c_int32), ("wg_per_cu", C.c_int32), ("remap_steps", C.c_int32)]
 
 
 class HistRetinexError(RuntimeError):

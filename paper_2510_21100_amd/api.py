@@ -64,8 +64,9 @@ class Workspace:
         self.max_images = max_images
         self.max_bins = max_bins
 
-    def set_schedule(self, tile_steps: int = 0, wg_per_cu: int = 0) -> None:
-        check(lib.hr_workspace_set_schedule(self.handle, C.byref(HrSchedule(tile_steps, wg_per_cu))))
+    def set_schedule(self, tile_steps: int = 0, wg_per_cu: int = 0, remap_steps: int = 0) -> None:
+        check(lib.hr_workspace_set_schedule(self.handle,
+                                            C.byref(HrSchedule(tile_steps, wg_per_cu, remap_steps))))
 
     def flags(self, clear: bool = False) -> int:
         f = C.c_uint32()

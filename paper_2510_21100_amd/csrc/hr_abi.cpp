@@ -32,8 +32,9 @@ hr_status fail(hr_status s, const std::string& msg) {
   } while (0)
 
 constexpr int kPlainTileSteps = 16;
-constexpr int kDefaultTileSteps = 16;
-constexpr int kDefaultWgPerCu = 2;
+constexpr int kDefaultTileSteps = 32;
+constexpr int kDefaultWgPerCu = 1;
+constexpr int kDefaultRemapSteps = 8;
 constexpr int kStaging = 2;
 
 size_t table_bytes(int max_images) {
@@ -54,7 +55,7 @@ struct hr_workspace {
   int max_images = 0;
   int max_bins = 0;
   int cu_count = 0;
-  hr_schedule sched{kDefaultTileSteps, kDefaultWgPerCu};
+  hr_schedule sched{kDefaultTileSteps, kDefaultWgPerCu, kDefaultRemapSteps};
   uint32_t* d_flags = nullptr;   // [0] sticky flags, [1] plain-hist ticket
   uint32_t* d_graw = nullptr;    // plain: raw gradient histogram scratch [2*max_bins]
   uint16_t* d_lut = nullptr;     // plain: LUT scratch [max_bins]
@@ -236,8 +237,10 @@ hr_status hr_workspace_set_schedule(hr_workspace* ws, const hr_schedule* sched) 
   if (!ws || !sched) return fail(HR_ERR_INVALID_ARG, "NULL argument");
   if (sched->tile_steps < 0 || sched->tile_steps > 4096) return fail(HR_ERR_INVALID_ARG, "tile_steps out of range");
   if (sched->wg_per_cu < 0 || sched->wg_per_cu > 8) return fail(HR_ERR_INVALID_ARG, "wg_per_cu out of range");
+  if (sched->remap_steps < 0 || sched->remap_steps > 4096) return fail(HR_ERR_INVALID_ARG, "remap_steps out of range");
   ws->sched.tile_steps = sched->tile_steps ? sched->tile_steps : kDefaultTileSteps;
   ws->sched.wg_per_cu = sched->wg_per_cu ? sched->wg_per_cu : kDefaultWgPerCu;
+  ws->sched.remap_steps = sched->remap_steps ? sched->remap_steps : kDefaultRemapSteps;
   return HR_OK;
 }
 
@@ -320,8 +323,9 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return descs[a].npix > descs[b].npix; });
-  const int64_t tile_px = (int64_t)ws->sched.tile_steps * hr::launch::step_px(bits);
-  int64_t tiles = 0;
+  const int64_t tile_px = (int64_t)ws->sched.tile_steps * hr::launch::batch_step_px(bits);
+  const int64_t rtile_px = (int64_t)ws->sched.remap_steps * hr::launch::batch_step_px(bits);
+  int64_t tiles = 0, rtiles = 0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int slot = ws->slot;
   if (ws->ev_used[slot]) HR_HIP(hipEventSynchronize(ws->ev[slot]));
@@ -331,14 +335,19 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     hr::ImgDesc d = descs[order[k]];
     d.ntiles = (int32_t)((d.npix + tile_px - 1) / tile_px);
     d.tile0 = (int32_t)tiles;
+    d.rtiles = (int32_t)((d.npix + rtile_px - 1) / rtile_px);
+    d.rtile0 = (int32_t)rtiles;
     tiles += d.ntiles;
-    if (tiles > (1LL << 30)) return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch: too many tiles");
+    rtiles += d.rtiles;
+    if (tiles + rtiles > (1LL << 30)) return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch: too many tiles");
     sd[k] = d;
   }
   hr::BatchHeader hdr{};
   hdr.n = n;
   hdr.total_tiles = (int32_t)tiles;
+  hdr.total_rtiles = (int32_t)rtiles;
   hdr.tile_px = tile_px;
+  hdr.rtile_px = rtile_px;
   hdr.params = solve_params(p);
   hdr.out = hr::BatchOut{luts, illum, refl, target};
   std::memcpy(stage, &hdr, sizeof(hdr));

@@ -22,21 +22,22 @@ namespace hr {
 constexpr int NT_PIX = 256;  // threads of a pixel-streaming workgroup
 
 using v4u = uint32_t __attribute__((ext_vector_type(4)));
+using v2u = uint32_t __attribute__((ext_vector_type(2)));
 constexpr uint32_t FLAG_VALUE_CLAMPED = 1u;
 constexpr uint32_t FLAG_HIST_MASS = 2u;
 
-// Per bit depth: element type, levels, pixels per thread per step, V-ring
-// entries (power of two) and copies of each LDS histogram (spreads
-// same-level atomics over banks).
+// Per bit depth: element type, levels and copies of each LDS histogram
+// (spreads same-level atomics over banks).
 template <int BITS> struct Cfg;
 template <> struct Cfg<8> {
   using pix_t = uint8_t;
-  static constexpr int BINS = 256, PX = 16, RING = 32768, REP = 4;
+  static constexpr int BINS = 256, REP = 4;
 };
 template <> struct Cfg<10> {
   using pix_t = uint16_t;
-  static constexpr int BINS = 1024, PX = 8, RING = 16384, REP = 1;
+  static constexpr int BINS = 1024, REP = 1;
 };
+
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -155,18 +156,77 @@ __device__ inline T block_scan(T* arr, int n, T* red) {
 // pixel loads
 // ---------------------------------------------------------------------------
 
+// Pixels per thread per step: 48 bytes of RGB per thread for 256-thread
+// workgroups, 24 bytes for 1024-thread workgroups (fewer registers).
+template <int BITS, int NT>
+struct Pix {
+  static constexpr int ESZ = BITS == 8 ? 1 : 2;
+  static constexpr int PX = (NT >= 1024 ? 24 : 48) / (3 * ESZ);
+  static constexpr int NW = 3 * PX * ESZ / 4;  // dwords of RGB per chunk
+  static constexpr int NV = PX * ESZ / 4;      // dwords of V per chunk
+  static constexpr int STEP = NT * PX;
+};
+
+// NW dwords from a pointer aligned to NW*4/3 bytes, as three vector loads.
+template <int NW, bool NONTEMPORAL>
+__device__ inline void load_words(const uint8_t* ptr, uint32_t (&w)[NW]) {
+  if constexpr (NW == 12) {
+    const v4u* s = reinterpret_cast<const v4u*>(ptr);
+    v4u a, b, c;
+    if (NONTEMPORAL) {
+      a = __builtin_nontemporal_load(s);
+      b = __builtin_nontemporal_load(s + 1);
+      c = __builtin_nontemporal_load(s + 2);
+    } else {
+      a = s[0];
+      b = s[1];
+      c = s[2];
+    }
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    w[8] = c.x; w[9] = c.y; w[10] = c.z; w[11] = c.w;
+  } else {
+    static_assert(NW == 6, "chunk of 24 or 48 bytes");
+    const v2u* s = reinterpret_cast<const v2u*>(ptr);
+    v2u a, b, c;
+    if (NONTEMPORAL) {
+      a = __builtin_nontemporal_load(s);
+      b = __builtin_nontemporal_load(s + 1);
+      c = __builtin_nontemporal_load(s + 2);
+    } else {
+      a = s[0];
+      b = s[1];
+      c = s[2];
+    }
+    w[0] = a.x; w[1] = a.y; w[2] = b.x; w[3] = b.y; w[4] = c.x; w[5] = c.y;
+  }
+}
+
+template <int NW>
+__device__ inline void store_words_nt(uint8_t* ptr, const uint32_t (&w)[NW]) {
+  if constexpr (NW == 12) {
+    v4u* d = reinterpret_cast<v4u*>(ptr);
+    __builtin_nontemporal_store(v4u{w[0], w[1], w[2], w[3]}, d);
+    __builtin_nontemporal_store(v4u{w[4], w[5], w[6], w[7]}, d + 1);
+    __builtin_nontemporal_store(v4u{w[8], w[9], w[10], w[11]}, d + 2);
+  } else {
+    v2u* d = reinterpret_cast<v2u*>(ptr);
+    __builtin_nontemporal_store(v2u{w[0], w[1]}, d);
+    __builtin_nontemporal_store(v2u{w[2], w[3]}, d + 1);
+    __builtin_nontemporal_store(v2u{w[4], w[5]}, d + 2);
+  }
+}
+
 // Value channel of PX consecutive pixels p .. p+PX-1 (n of them valid).
-// Vectorised: three 16-byte loads cover the 48 bytes of the chunk.
-template <int BITS>
-__device__ inline void load_values(const ImgDesc& d, int64_t p, int n, uint32_t (&v)[Cfg<BITS>::PX],
+template <int BITS, int NT>
+__device__ inline void load_values(const ImgDesc& d, int64_t p, int n, uint32_t (&v)[Pix<BITS, NT>::PX],
                                    uint32_t& clamped) {
   using pix_t = typename Cfg<BITS>::pix_t;
-  constexpr int PX = Cfg<BITS>::PX;
+  constexpr int PX = Pix<BITS, NT>::PX, NW = Pix<BITS, NT>::NW;
   constexpr uint32_t TOP = (1u << BITS) - 1;
   if (d.in_vec && n == PX) {
-    const uint4* src = reinterpret_cast<const uint4*>(d.in + p * 3 * (int64_t)sizeof(pix_t));
-    const uint4 a = src[0], b = src[1], c = src[2];
-    const uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+    uint32_t w[NW];
+    load_words<NW, false>(d.in + p * 3 * (int64_t)sizeof(pix_t), w);
 #pragma unroll
     for (int i = 0; i < PX; ++i) {
       uint32_t x = umax3(lane_of<pix_t>(w, 3 * i), lane_of<pix_t>(w, 3 * i + 1),
@@ -207,9 +267,19 @@ __device__ inline void load_values(const ImgDesc& d, int64_t p, int n, uint32_t 
 // trails the loads by one row.
 // ---------------------------------------------------------------------------
 
-template <int BITS>
+// Widest supported image and the V-ring (entries, a power of two) for a
+// workgroup of NT threads: the ring must hold one image row plus two steps.
+template <int BITS> struct MaxWidth { static constexpr int value = BITS == 8 ? 16384 : 8192; };
+constexpr int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+template <int BITS, int NT>
 struct HistSmem {
-  static constexpr int BINS = Cfg<BITS>::BINS, REP = Cfg<BITS>::REP, RING = Cfg<BITS>::RING;
+  static constexpr int BINS = Cfg<BITS>::BINS, REP = Cfg<BITS>::REP;
+  static constexpr int RING = pow2_at_least(MaxWidth<BITS>::value + 2 * Pix<BITS, NT>::STEP);
   using pix_t = typename Cfg<BITS>::pix_t;
   static constexpr int RING_BYTES = RING * (int)sizeof(pix_t);
   uint32_t hs[BINS * REP];
@@ -218,26 +288,34 @@ struct HistSmem {
   uint32_t clamped;
 };
 
-// 16 bytes starting at an arbitrary byte offset of the ring.
-__device__ inline uint4 ring_read16(const uint32_t* ring, uint32_t byteoff) {
+// NV dwords starting at an arbitrary byte offset of the ring.
+template <int NV>
+__device__ inline void ring_read(const uint32_t* ring, uint32_t byteoff, uint32_t (&out)[NV]) {
   const uint32_t b = byteoff >> 2, sh = byteoff & 3;
-  const uint32_t d0 = ring[b], d1 = ring[b + 1], d2 = ring[b + 2], d3 = ring[b + 3], d4 = ring[b + 4];
-  uint4 r;
-  r.x = __builtin_amdgcn_alignbyte(d1, d0, sh);
-  r.y = __builtin_amdgcn_alignbyte(d2, d1, sh);
-  r.z = __builtin_amdgcn_alignbyte(d3, d2, sh);
-  r.w = __builtin_amdgcn_alignbyte(d4, d3, sh);
-  return r;
+  uint32_t dw[NV + 1];
+#pragma unroll
+  for (int k = 0; k <= NV; ++k) dw[k] = ring[b + k];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = __builtin_amdgcn_alignbyte(dw[k + 1], dw[k], sh);
+}
+
+template <int NV>
+__device__ inline void ring_write(uint32_t* ring, uint32_t byteoff, const uint32_t (&w)[NV]) {
+  if constexpr (NV == 4) {
+    *reinterpret_cast<v4u*>(reinterpret_cast<uint8_t*>(ring) + byteoff) = v4u{w[0], w[1], w[2], w[3]};
+  } else {
+    *reinterpret_cast<v2u*>(reinterpret_cast<uint8_t*>(ring) + byteoff) = v2u{w[0], w[1]};
+  }
 }
 
 template <int BITS, int NT>
-__device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BITS>& sm,
+__device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BITS, NT>& sm,
                           uint32_t* __restrict__ g_hs, uint32_t* __restrict__ g_graw) {
   using pix_t = typename Cfg<BITS>::pix_t;
-  constexpr int BINS = Cfg<BITS>::BINS, PX = Cfg<BITS>::PX, REP = Cfg<BITS>::REP;
-  constexpr int RING = Cfg<BITS>::RING;
-  constexpr int RING_BYTES = HistSmem<BITS>::RING_BYTES;
-  constexpr int STEP = NT * PX;
+  constexpr int BINS = Cfg<BITS>::BINS, REP = Cfg<BITS>::REP;
+  constexpr int PX = Pix<BITS, NT>::PX, NV = Pix<BITS, NT>::NV, STEP = Pix<BITS, NT>::STEP;
+  constexpr int RING = HistSmem<BITS, NT>::RING;
+  constexpr int RING_BYTES = HistSmem<BITS, NT>::RING_BYTES;
   constexpr int ESZ = (int)sizeof(pix_t);
   const int t = threadIdx.x;
   const int rep = t & (REP - 1);
@@ -260,17 +338,15 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
       const int n = (int)max((int64_t)0, min((int64_t)PX, E - p));
       if (n > 0) {
         uint32_t v[PX];
-        load_values<BITS>(d, p, n, v, clamped);
-        uint32_t packed[4] = {0, 0, 0, 0};
+        load_values<BITS, NT>(d, p, n, v, clamped);
+        uint32_t packed[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) packed[k] = 0;
 #pragma unroll
         for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
         const uint32_t boff = (uint32_t)(((p - P0) & (RING - 1)) * ESZ);
-        uint4* dst = reinterpret_cast<uint4*>(reinterpret_cast<uint8_t*>(sm.ring) + boff);
-        *dst = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-        if (boff < 64) {
-          uint4* mir = reinterpret_cast<uint4*>(reinterpret_cast<uint8_t*>(sm.ring) + RING_BYTES + boff);
-          *mir = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-        }
+        ring_write<NV>(sm.ring, boff, packed);
+        if (boff < 64) ring_write<NV>(sm.ring, RING_BYTES + boff, packed);
         const int nh = (int)max((int64_t)0, min((int64_t)n, P1 - p));
 #pragma unroll
         for (int i = 0; i < PX; ++i)
@@ -284,15 +360,15 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
     const int n = (int)max((int64_t)0, min((int64_t)PX, dend - q));
     if (n > 0) {
       const uint32_t boff = (uint32_t)(((q - P0) & (RING - 1)) * ESZ);
-      const uint4 own4 = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint8_t*>(sm.ring) + boff);
-      const uint32_t own[4] = {own4.x, own4.y, own4.z, own4.w};
+      uint32_t own[NV];
+      ring_read<NV>(sm.ring, boff, own);  // aligned: the shift is 0
       const uint32_t rboff = boff + PX * ESZ;  // <= RING_BYTES: mirror covers it
       const uint32_t right_last =
           ESZ == 1 ? (uint32_t)reinterpret_cast<const uint8_t*>(sm.ring)[rboff]
                    : (uint32_t)reinterpret_cast<const uint16_t*>(sm.ring)[rboff >> 1];
       const uint32_t dboff = (uint32_t)(((q + W - P0) & (RING - 1)) * ESZ);
-      const uint4 dn4 = ring_read16(sm.ring, dboff);
-      const uint32_t dn[4] = {dn4.x, dn4.y, dn4.z, dn4.w};
+      uint32_t dn[NV];
+      ring_read<NV>(sm.ring, dboff, dn);
       int x = (int)(q % W);
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
@@ -325,6 +401,10 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
     for (int r = 0; r < REP; ++r) s += sm.hg[k * REP + r];
     if (s) atomicAdd(&g_graw[k], s);
   }
+  // every thread's merge is performed before any thread of the workgroup
+  // signals completion of the tile
+  __threadfence();
+  __syncthreads();
 }
 
 // Gradient histogram onto the l levels: raw level j -> round-half-up(j(l-1)/gmax).
@@ -367,16 +447,13 @@ __device__ inline uint32_t remap_channel(uint32_t c, uint32_t v, uint2 e) {
 template <int BITS, int NT>
 __device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const uint2* tab) {
   using pix_t = typename Cfg<BITS>::pix_t;
-  constexpr int PX = Cfg<BITS>::PX;
-  constexpr int STEP = NT * PX;
+  constexpr int PX = Pix<BITS, NT>::PX, NW = Pix<BITS, NT>::NW, STEP = Pix<BITS, NT>::STEP;
   constexpr uint32_t TOP = (1u << BITS) - 1;
   for (int64_t p = P0 + (int64_t)threadIdx.x * PX; p < P1; p += STEP) {
     const int n = (int)min((int64_t)PX, P1 - p);
     if (d.in_vec && d.out_vec && n == PX) {
-      const v4u* src = reinterpret_cast<const v4u*>(d.in + p * 3 * (int64_t)sizeof(pix_t));
-      const v4u a = __builtin_nontemporal_load(src), b = __builtin_nontemporal_load(src + 1),
-                c = __builtin_nontemporal_load(src + 2);
-      uint32_t w[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+      uint32_t w[NW];
+      load_words<NW, true>(d.in + p * 3 * (int64_t)sizeof(pix_t), w);
 #pragma unroll
       for (int i = 0; i < PX; ++i) {
         uint32_t r = lane_of<pix_t>(w, 3 * i), g = lane_of<pix_t>(w, 3 * i + 1),
@@ -392,10 +469,7 @@ __device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const uint2
         set_lane<pix_t>(w, 3 * i + 1, remap_channel<BITS>(g, v, e));
         set_lane<pix_t>(w, 3 * i + 2, remap_channel<BITS>(bl, v, e));
       }
-      v4u* dst = reinterpret_cast<v4u*>(d.out + p * 3 * (int64_t)sizeof(pix_t));
-      __builtin_nontemporal_store(v4u{w[0], w[1], w[2], w[3]}, dst);
-      __builtin_nontemporal_store(v4u{w[4], w[5], w[6], w[7]}, dst + 1);
-      __builtin_nontemporal_store(v4u{w[8], w[9], w[10], w[11]}, dst + 2);
+      store_words_nt<NW>(d.out + p * 3 * (int64_t)sizeof(pix_t), w);
     } else {
       int64_t y = p / d.W;
       int x = (int)(p - y * d.W);
@@ -503,191 +577,469 @@ __device__ void build_lut(const uint32_t* hS, const float* target, LutSmem<BINS,
 
 // ---------------------------------------------------------------------------
 // solver
+//
+// Histograms are kept compacted over their occupied levels: A = supp H_C(S)
+// (illumination levels a), B = supp H_C(grad S) (reflectance levels b).  The
+// updates keep L and R zero outside A and B, and every cell outside A x B
+// contributes an exact zero, so the sweeps run over A x B only:
+//   class sweep  d_m = sum_{index(a,b)=m} L_a R_b       (Eq. 8 with Eq. 6)
+//   column sweep u_b = sum_a L_a^2 rho_index(a,b)        (Eq. 13, K = L R / d)
+//   row sweep    v_a = sum_b R'_b R_b rho_index(a,b)     (Eq. 12)
+// with rho_m = s_m / d_m, so that K_ab s_index(a,b) = L_a R_b rho_index(a,b).
+//
+// The loops are shaped for issue rate: every lane of a wave runs the same
+// trip count (chunks and slices are padded with cells that point at a zero),
+// the class of a cell comes from a table built once per image, and partial
+// sums are combined inside a wave (butterflies, segmented scans).  Every sum
+// has a fixed association, so results do not depend on timing.
 // ---------------------------------------------------------------------------
 
+template <int BINS> struct CellT;
+template <> struct CellT<256> {
+  using type = uint16_t;
+  static constexpr int SHIFT = 8;
+};
+template <> struct CellT<1024> {
+  using type = uint32_t;
+  static constexpr int SHIFT = 10;
+};
+
 template <int BINS, int NT>
-struct SolveSmem {
-  float s[BINS], g[BINS];     // image / gradient histograms, probability units
-  float lv[BINS], rv[BINS];   // current illumination / reflectance histograms
-  float rho[BINS];            // s_m / d_m per class
-  float acc[BINS];            // output of a segmented sweep
-  float rn[BINS];             // R' of Eq. (13) before rescaling
-  union {
-    struct {
-      float l2[BINS];  // L_a^2, later L' of Eq. (12) before rescaling
-      float w[BINS];   // R'_b R_b
-    } it;
-    unsigned long long tacc[BINS];  // fixed-point class sums of Eq. (20)
-  } u;
-  int32_t off[3][BINS + 1];   // segment offsets: rows, columns, classes
-  uint16_t A[BINS], B[BINS];  // occupied levels of s and g, ascending
-  float first_sum[NT], last_sum[NT];
-  float redf[NT / 64];
+struct SolveCore {
+  static constexpr int RMAX = BINS == 256 ? 2 : 1;  // rounds of chunks per lane
+  static constexpr int KS = BINS == 256 ? 8 : 1;    // row slices per class in the build
+  static constexpr int PAD = BINS + 256;            // zero padding of the sweep inputs (G * L <= 2n + 256)
+  float sc[BINS], gc[BINS];                         // s, g on A, B
+  float lc[BINS + 4], rc[BINS + 4];                 // current L on A, R on B; [n] = 0
+  alignas(16) float l2c[BINS + PAD];                // L^2 on A (zero padded), later L'
+  alignas(16) float wc[BINS + PAD];                 // R' R on B (zero padded)
+  float rn[BINS];                                   // R' of Eq. (13) on B
+  float sd[BINS];                                   // s by level (dense)
+  float inv2a[BINS];                                // 1 / (2a) for the rows of A
+  alignas(8) float rho[BINS + 4];                   // s_m / d_m by class
+  uint16_t A[BINS], B[BINS];
+  int32_t off[BINS + 1];                            // first chunk of class m
+  int32_t csz[BINS];                                // cells of class m
+  int32_t PA[BINS + 1], PB[BINS + 1];               // occupied levels below a / b
+  int32_t cnt[KS * BINS];                           // cells per (row slice, class)
+  int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
+  float redf[4][NT / 64];
   uint64_t redu[NT / 64];
   int32_t redi[NT / 64];
-  int32_t nA, nB, nc;
-  int32_t C[3];
+  int32_t nA, nB, nc, C, CS, R, nAp, nBp;           // CS: cell stride of a chunk
+  int32_t cells_lds, tab_lds, use_list;
+};
+
+// The class list and the class tables take the LDS left in `budget` bytes.
+template <int BINS, int NT, int BUDGET>
+struct SolveSmem : SolveCore<BINS, NT> {
+  static constexpr int FREE = BUDGET - (int)sizeof(SolveCore<BINS, NT>) > 64
+                                  ? BUDGET - (int)sizeof(SolveCore<BINS, NT>)
+                                  : 64;
+  alignas(16) uint32_t spare[FREE / 4];
+  // the target sums (BINS x u64) and the gamma table (BINS doubles) reuse spare
+  static_assert(FREE >= 16 * BINS, "LDS budget too small for the solver");
 };
 
 // index(a, b) of Eq. (10): nearest level of a*b/(l-1)^2 on the grid k/(l-1),
 // i.e. round(a*b/(l-1)); l-1 is odd so there are no ties.
 template <int BINS>
 __device__ inline int class_of(int a, int b) {
-  constexpr int D = BINS - 1;
-  return (2 * a * b + D) / (2 * D);
+  constexpr uint32_t D = BINS - 1;
+  return (int)((2u * (uint32_t)a * (uint32_t)b + D) / (2u * D));
 }
 
-__device__ inline uint32_t pack_cell(int key, int x, int y) {
-  return ((uint32_t)key << 20) | ((uint32_t)x << 10) | (uint32_t)y;
+// floor(x / y) from a float reciprocal of y, corrected to the exact value
+// (the estimate is within one of it for x < 2^22).
+__device__ inline uint32_t div_floor(uint32_t x, uint32_t y, float inv_y) {
+  uint32_t q = (uint32_t)((float)x * inv_y);
+  if ((q + 1u) * y <= x) ++q;
+  if (q * y > x) --q;
+  return q;
 }
 
-// position of the i-th entry of a list stored chunk-interleaved for
-// coalesced reads: chunk t (entries [tC, tC+C)) is column t
+// Reflectance levels b of class m in illumination row a = A[i]: the b with
+// (2m-1)(l-1) < 2ab < (2m+1)(l-1), as a compacted index range [jlo, jhi) of
+// B.  Both bounds are odd multiples of l-1 over an even number, never
+// integers, so the floors below are the exact bounds.
+template <int BINS, typename SM>
+__device__ inline void class_run(const SM& sm, int i, int m, int& jlo, int& jhi) {
+  constexpr uint32_t D = BINS - 1;
+  const int a = sm.A[i];
+  if (a == 0) {
+    jlo = 0;
+    jhi = m == 0 ? sm.nB : 0;
+    return;
+  }
+  const uint32_t two_a = 2u * (uint32_t)a;
+  const float inv = sm.inv2a[i];
+  const uint32_t blo = m == 0 ? 0u : div_floor((2u * m - 1u) * D, two_a, inv) + 1u;
+  const uint32_t bhi = min(div_floor((2u * m + 1u) * D, two_a, inv), (uint32_t)(BINS - 1));
+  if (blo > bhi) {
+    jlo = jhi = 0;
+    return;
+  }
+  jlo = sm.PB[blo];
+  jhi = sm.PB[bhi + 1];
+}
+
 template <int NT>
-__device__ inline int list_pos(int i, int C) {
-  return (i % C) * NT + i / C;
+__device__ inline void wave_partial(float x, float* red) {
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
 }
 
-// out[k] = sum over list entries with key k of X[x] * Y[y], for every key
-// (0 for empty segments).  Each thread sums one chunk of C consecutive
-// entries; segments crossing chunk borders are completed from the chunk
-// partials in chunk order.  Fixed association -> deterministic.
-template <int BINS, int NT>
-__device__ void seg_sweep(const uint32_t* __restrict__ list, int nc, int C, const int32_t* off,
-                          const float* X, const float* Y, float* out, float* first_sum, float* last_sum) {
-  const int t = threadIdx.x;
-  const int i0 = t * C, i1 = min(i0 + C, nc);
-  if (i0 < i1) {
-    uint32_t e = list[(0) * NT + t];
-    int cur = (int)(e >> 20);
-    float acc = 0.f;
-    bool first = true;
-    for (int i = i0, s = 0;;) {
-      acc = fmaf(X[(e >> 10) & 1023u], Y[e & 1023u], acc);
-      ++i;
-      ++s;
-      int k = -1;
-      if (i < i1) {
-        e = list[s * NT + t];
-        k = (int)(e >> 20);
-      }
-      if (k != cur) {
-        const int o1 = off[cur], o2 = off[cur + 1];
-        if (o1 >= i0 && o2 <= i1) {
-          out[cur] = acc;
-        } else {
-          if (first) first_sum[t] = acc;
-          if (k < 0) last_sum[t] = acc;
-        }
-        if (k < 0) break;
-        cur = k;
-        acc = 0.f;
-        first = false;
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = t; k < BINS; k += NT) {
-    const int o1 = off[k], o2 = off[k + 1];
-    if (o1 == o2) {
-      out[k] = 0.f;
-      continue;
-    }
-    const int t1 = o1 / C, t2 = (o2 - 1) / C;
-    if (t1 == t2) continue;
-    float s = last_sum[t1];
-    for (int u = t1 + 1; u < t2; ++u) s += first_sum[u];
-    s += first_sum[t2];
-    out[k] = s;
-  }
-  __syncthreads();
+template <int NT>
+__device__ inline float block_read(const float* red) {
+  float s = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) s += red[i];
+  return s;
 }
 
-// Builds the three segment lists of the active cells (a in supp s, b in
-// supp g, s[index(a,b)] > 0): by row a, by column b and by class m.
-// Cells outside these sets contribute exact zeros to every sweep.
-template <int BINS, int NT>
-__device__ void build_lists(SolveSmem<BINS, NT>& sm, uint32_t* lists) {
+// largest power of two <= x (x >= 1), capped at 64
+__device__ inline int pow2_floor64(int x) {
+  int p = 1;
+  while (p * 2 <= x && p < 64) p *= 2;
+  return p;
+}
+
+template <int BINS, int NT, int BUDGET>
+__device__ inline typename CellT<BINS>::type* cell_store(SolveSmem<BINS, NT, BUDGET>& sm) {
+  return reinterpret_cast<typename CellT<BINS>::type*>(sm.spare);
+}
+
+// Class tables (256 levels only), after the class list in LDS: tab[i*nBp + j]
+// = index(A[i], B[j]) for the row sweep and tabT[j*nAp + i] for the column
+// sweep, one byte per cell.
+template <int BINS, int NT, int BUDGET>
+__device__ inline uint8_t* class_table(SolveSmem<BINS, NT, BUDGET>& sm) {
+  using cell_t = typename CellT<BINS>::type;
+  return reinterpret_cast<uint8_t*>(sm.spare) + (((size_t)sm.R * NT * sm.CS * sizeof(cell_t) + 15) & ~(size_t)15);
+}
+
+// Class-major list of the cells (i, j) of A x B whose class has s_m > 0
+// (other classes have rho = 0 and their totals are never used), cut into
+// chunks of exactly C cells (C a multiple of 4; the last chunk of a class
+// padded with a cell pointing at zeros).  Chunks are laid out over R rounds of
+// NT lanes; the chunks of a class are consecutive and never cross a 64-chunk
+// boundary, so a class is summed inside one wave of one round.  Within a
+// class the cells are ordered by row slice, row and column.  Chunk u holds
+// its cells contiguously from u * CS.  256 levels only.
+template <int BINS, int NT, int BUDGET>
+__device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells,
+                                 int64_t gcap) {
+  using cell_t = typename CellT<BINS>::type;
+  constexpr int SH = CellT<BINS>::SHIFT;
+  constexpr int MAXCH = 32;  // chunks per class
+  constexpr int RMAX = SolveCore<BINS, NT>::RMAX, KS = SolveCore<BINS, NT>::KS;
+  static_assert(BINS <= NT * RMAX / 2, "every class must get a chunk");
   const int t = threadIdx.x;
-  constexpr int MAXCH = 32;  // at most this many chunks per segment
   const int nA = sm.nA, nB = sm.nB;
-  for (int k = t; k < 3 * (BINS + 1); k += NT) (&sm.off[0][0])[k] = 0;
-  __syncthreads();
-  for (int q = t; q < nA * nB; q += NT) {
-    const int i = q / nB, j = q - (q / nB) * nB;
-    const int a = sm.A[i], b = sm.B[j];
-    const int m = class_of<BINS>(a, b);
-    if (sm.s[m] > 0.f) {
-      atomicAdd(&sm.off[0][a], 1);
-      atomicAdd(&sm.off[1][b], 1);
-      atomicAdd(&sm.off[2][m], 1);
-    }
-  }
-  __syncthreads();
-  int32_t mx[3];
-  for (int r = 0; r < 3; ++r) {
-    int m = 0;
-    for (int k = t; k < BINS; k += NT) m = max(m, sm.off[r][k]);
-    mx[r] = block_max<NT>(m, sm.redi);
-  }
-  int nc = 0;
-  for (int r = 0; r < 3; ++r) nc = block_scan<NT, int32_t>(sm.off[r], BINS + 1, sm.redi);
-  if (t == 0) {
-    sm.nc = nc;
-    for (int r = 0; r < 3; ++r) sm.C[r] = max(1, max((nc + NT - 1) / NT, (mx[r] + MAXCH - 1) / MAXCH));
-  }
-  __syncthreads();
-  const int Cr = sm.C[0], Cc = sm.C[1], Cm = sm.C[2];
-  uint32_t* Lr = lists;
-  uint32_t* Lc = lists + BINS * BINS;
-  uint32_t* Lm = lists + 2 * BINS * BINS;
-  for (int i = t; i < nA; i += NT) {  // rows, b ascending
-    const int a = sm.A[i];
-    int pos = sm.off[0][a];
-    for (int j = 0; j < nB; ++j) {
-      const int b = sm.B[j];
-      const int m = class_of<BINS>(a, b);
-      if (sm.s[m] > 0.f) Lr[list_pos<NT>(pos++, Cr)] = pack_cell(a, b, m);
-    }
-  }
-  for (int j = t; j < nB; j += NT) {  // columns, a ascending
-    const int b = sm.B[j];
-    int pos = sm.off[1][b];
-    for (int i = 0; i < nA; ++i) {
-      const int a = sm.A[i];
-      const int m = class_of<BINS>(a, b);
-      if (sm.s[m] > 0.f) Lc[list_pos<NT>(pos++, Cc)] = pack_cell(b, a, m);
-    }
-  }
-  for (int m = t; m < BINS; m += NT) {  // classes, (a, b) ascending
-    int pos = sm.off[2][m];
-    if (sm.off[2][m + 1] == pos) continue;
-    for (int i = 0; i < nA; ++i) {
-      const int a = sm.A[i];
-      if (a < m) continue;  // index(a, b) <= a
-      // class is non-decreasing in b: find the run of class m in row a
-      int lo = 0, hi = nB;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (class_of<BINS>(a, sm.B[mid]) >= m) hi = mid; else lo = mid + 1;
+  // cells per (class, row slice): rows with a >= m, split into KS slices
+  for (int q = t; q < KS * BINS; q += NT) {
+    const int m = q % BINS, k = q / BINS;
+    int c = 0;
+    if (sm.sd[m] > 0.f) {
+      const int r0 = sm.PA[m], nr = nA - r0;
+      const int i0 = r0 + (k * nr) / KS, i1 = r0 + ((k + 1) * nr) / KS;
+      for (int i = i0; i < i1; ++i) {
+        int jlo, jhi;
+        class_run<BINS>(sm, i, m, jlo, jhi);
+        c += jhi - jlo;
       }
-      int j = lo;
-      for (; j < nB && class_of<BINS>(a, sm.B[j]) == m; ++j) Lm[list_pos<NT>(pos++, Cm)] = pack_cell(m, a, sm.B[j]);
+    }
+    sm.cnt[k * BINS + m] = c;
+  }
+  for (int u = t; u < RMAX * NT; u += NT) sm.chunk_cls[u] = -1;
+  __syncthreads();
+  int mx = 0, tot = 0;
+  for (int m = t; m < BINS; m += NT) {
+    int c = 0;
+    for (int k = 0; k < KS; ++k) c += sm.cnt[k * BINS + m];
+    sm.csz[m] = c;
+    mx = max(mx, c);
+    tot += c;
+  }
+  mx = block_max<NT>(mx, sm.redi);
+  const int nc = block_sum<NT>(tot, sm.redi);
+  if (t < 64) {
+    // one wave lays the chunks out: class sizes in registers, the position
+    // carried as a wave-uniform scalar.  The chunk size starts at about one
+    // round of chunks and grows until the padded layout fits RMAX rounds; it
+    // fits at the latest when every class has one chunk (C >= mx): at most
+    // BINS chunks and no padding.
+    constexpr int Q = (BINS + 63) / 64;
+    const int lane = t;
+    int cs[Q], offs[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      cs[q] = sm.csz[q * 64 + lane];
+      offs[q] = 0;
+    }
+    int C = max(4, max((mx + MAXCH - 1) / MAXCH, (nc + NT - 1) / NT));
+    C = (C + 3) & ~3;
+    int pos = 0;
+    for (;;) {
+      pos = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int nv = (cs[q] + C - 1) / C;
+        for (int l = 0; l < 64; ++l) {
+          const int n = __builtin_amdgcn_readlane(nv, l);
+          if (n && (pos & 63) + n > 64) pos = (pos + 63) & ~63;
+          if (lane == l) offs[q] = pos;
+          pos += n;
+        }
+      }
+      if (pos <= RMAX * NT || C >= mx) break;
+      C = min((mx + 3) & ~3, (C + C / 2 + 3) & ~3);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sm.off[q * 64 + lane] = offs[q];
+    if (lane == 0) {
+      sm.off[BINS] = pos;
+      sm.nc = nc;
+      sm.C = C;
+      sm.CS = (C & 7) == 4 ? C : C + 4;  // C = 4 mod 8: conflict-free 8-byte reads
+      sm.R = max(1, (pos + NT - 1) / NT);
+      const int64_t ncells = (int64_t)sm.R * NT * sm.CS;
+      const int64_t cell_bytes = ncells * sizeof(cell_t);
+      sm.cells_lds = cell_bytes <= (int64_t)sizeof(sm.spare) ? 1 : 0;
+      sm.use_list = (sm.cells_lds || ncells <= gcap) ? 1 : 0;
+      sm.nAp = (nA + 3) & ~3;
+      sm.nBp = (nB + 3) & ~3;
+      const int64_t tab_bytes = (int64_t)nA * sm.nBp + (int64_t)nB * sm.nAp + 16;
+      sm.tab_lds = (sm.cells_lds && ((cell_bytes + 15) & ~15) + tab_bytes <= (int64_t)sizeof(sm.spare)) ? 1 : 0;
     }
   }
   __syncthreads();
+  if (!sm.use_list) return;  // the solver sums the classes without a list
+  const int C = sm.C, CS = sm.CS, R = sm.R;
+  cell_t* cells = sm.cells_lds ? cell_store(sm) : gcells;
+  const cell_t zero_cell = (cell_t)(nA | (nB << SH));  // lc[nA] = rc[nB] = 0
+  for (int q = t; q < R * NT * CS; q += NT) cells[q] = zero_cell;
+  for (int m = t; m < BINS; m += NT) {
+    const int c = sm.csz[m];
+    for (int u = 0; u * C < c; ++u) sm.chunk_cls[sm.off[m] + u] = (int16_t)m;
+  }
+  __syncthreads();
+  for (int q = t; q < KS * BINS; q += NT) {
+    const int m = q % BINS, k = q / BINS;
+    if (!sm.cnt[k * BINS + m]) continue;
+    int c = 0;  // cells of class m in earlier slices
+    for (int kk = 0; kk < k; ++kk) c += sm.cnt[kk * BINS + m];
+    int chunk = sm.off[m] + c / C, slot = c - (c / C) * C;
+    const int r0 = sm.PA[m], nr = nA - r0;
+    const int i0 = r0 + (k * nr) / KS, i1 = r0 + ((k + 1) * nr) / KS;
+    for (int i = i0; i < i1; ++i) {
+      int jlo, jhi;
+      class_run<BINS>(sm, i, m, jlo, jhi);
+      for (int j = jlo; j < jhi; ++j) {
+        cells[chunk * CS + slot] = (cell_t)(i | (j << SH));
+        if (++slot == C) {
+          slot = 0;
+          ++chunk;
+        }
+      }
+    }
+  }
+  if (sm.tab_lds) {
+    uint8_t* tab = class_table(sm);
+    uint8_t* tabT = tab + nA * sm.nBp;
+    const int nAp = sm.nAp, nBp = sm.nBp;
+    for (int q = t; q < nA * nBp; q += NT) {
+      const int i = q / nBp, j = q - i * nBp;
+      tab[q] = j < nB ? (uint8_t)class_of<BINS>(sm.A[i], sm.B[j]) : (uint8_t)0;
+    }
+    for (int q = t; q < nB * nAp; q += NT) {
+      const int j = q / nAp, i = q - j * nAp;
+      tabT[q] = i < nA ? (uint8_t)class_of<BINS>(sm.A[i], sm.B[j]) : (uint8_t)0;
+    }
+  }
+  __syncthreads();
+}
+
+// The Alg. 1 loop.  LIST: class totals from the class list (else per-class
+// gathers over row runs); CELLS_LDS / TAB: where the list and the class
+// tables live, so that every access compiles to its address space.
+template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
+__device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
+                        const SolveParams& p) {
+  using cell_t = typename CellT<BINS>::type;
+  constexpr int SH = CellT<BINS>::SHIFT;
+  constexpr uint32_t MASK = (1u << SH) - 1;
+  constexpr int PAD = SolveCore<BINS, NT>::PAD;
+  const int t = threadIdx.x, lane = t & 63;
+  const int nA = sm.nA, nB = sm.nB, C = sm.C, CS = sm.CS, R = sm.R;
+  const cell_t* cells = CELLS_LDS ? cell_store(sm) : gcells;
+  const uint8_t* tab = class_table(sm);
+  const uint8_t* tabT = tab + nA * sm.nBp;
+  const int nAp = sm.nAp, nBp = sm.nBp;
+  // dense sweeps: output o split over G lanes (a power of two); slice k covers
+  // L inputs (a multiple of 4), zero-padded past the end
+  const int Gc = nB <= NT ? pow2_floor64(NT / nB) : 1;
+  const int Gr = nA <= NT ? pow2_floor64(NT / nA) : 1;
+  const int Lc = ((nA + Gc - 1) / Gc + 3) & ~3, Lr = ((nB + Gr - 1) / Gr + 3) & ~3;
+  for (int q = t; q < BINS + PAD; q += NT) {
+    if (q >= nA) sm.l2c[q] = 0.f;
+    if (q >= nB) sm.wc[q] = 0.f;
+  }
+  for (int m = t; m < BINS + 4; m += NT) sm.rho[m] = 0.f;
+  if (t == 0) {
+    sm.lc[nA] = 0.f;
+    sm.rc[nB] = 0.f;
+  }
+  __syncthreads();
+
+  for (int it = 0; it < p.iters; ++it) {
+    // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m
+    {
+      if constexpr (LIST) {
+        // one chunk per lane and round; a class is summed inside its wave
+        for (int r = 0; r < R; ++r) {
+          const int u = r * NT + t;
+          const cell_t* cp = cells + (size_t)u * CS;
+          float acc = 0.f;
+          for (int k = 0; k < C; k += 4) {
+            uint32_t e[4];
+            if constexpr (sizeof(cell_t) == 2) {
+              const v2u w = *reinterpret_cast<const v2u*>(cp + k);
+              e[0] = w.x & 0xffffu; e[1] = w.x >> 16; e[2] = w.y & 0xffffu; e[3] = w.y >> 16;
+            } else {
+              const v4u w = *reinterpret_cast<const v4u*>(cp + k);
+              e[0] = w.x; e[1] = w.y; e[2] = w.z; e[3] = w.w;
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x) acc = fmaf(sm.lc[e[x] & MASK], sm.rc[e[x] >> SH], acc);
+          }
+          const int cls = sm.chunk_cls[u];
+          const int seg0 = cls >= 0 ? (sm.off[cls] & 63) : 64;  // lane of the class's first chunk
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {  // inclusive segmented scan over the class's lanes
+            const float y = __shfl_up(acc, o, 64);
+            if (lane - o >= seg0) acc += y;
+          }
+          if (cls >= 0 && (u - sm.off[cls] + 1) * C >= sm.csz[cls])
+            sm.rho[cls] = acc > 0.f ? sm.sd[cls] / acc : 0.f;
+        }
+      } else {
+        // one class per lane: rows of A, each contributing a run of B
+        for (int m = t; m < BINS; m += NT) {
+          if (sm.sd[m] <= 0.f) continue;
+          float d = 0.f;
+          for (int i = sm.PA[m]; i < nA; ++i) {
+            int jlo, jhi;
+            class_run<BINS>(sm, i, m, jlo, jhi);
+            float run = 0.f;
+            for (int j = jlo; j < jhi; ++j) run += sm.rc[j];
+            d = fmaf(sm.lc[i], run, d);
+          }
+          sm.rho[m] = d > 0.f ? sm.sd[m] / d : 0.f;
+        }
+      }
+      float ql = 0.f;
+      for (int i = t; i < nA; i += NT) {
+        const float l = sm.lc[i];
+        sm.l2c[i] = l * l;
+        ql += l * l;
+      }
+      wave_partial<NT>(ql, sm.redf[0]);
+    }
+    __syncthreads();
+    // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta)
+    {
+      const float denR = block_read<NT>(sm.redf[0]) + p.beta;
+      float qr = 0.f, sr = 0.f;
+      for (int base = 0; base < nB * Gc; base += NT) {
+        const int q = base + t;
+        const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
+        const int s0 = k * Lc;  // a multiple of 4
+        float acc = 0.f;
+        if constexpr (TAB) {
+          const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
+          for (int s = s0; s < s0 + Lc; s += 4) {
+            const v4u xv = *reinterpret_cast<const v4u*>(&sm.l2c[s]);
+            const uint32_t cls4 = s < nAp ? trow[s >> 2] : 0u;
+            acc = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], acc);
+          }
+        } else {
+          const int b = sm.B[o];
+          for (int s = s0; s < s0 + Lc; ++s)
+            acc = fmaf(sm.l2c[s], sm.rho[class_of<BINS>(sm.A[min(s, nA - 1)], b)], acc);
+        }
+        for (int w = Gc >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
+        if (k == 0 && q / Gc < nB) {
+          const float r = sm.rc[o];
+          const float rn = (r * acc + p.beta * sm.gc[o]) / denR;
+          sm.rn[o] = rn;
+          sm.wc[o] = rn * r;
+          qr += rn * rn;
+          sr += rn;
+        }
+      }
+      wave_partial<NT>(qr, sm.redf[1]);
+      wave_partial<NT>(sr, sm.redf[2]);
+    }
+    __syncthreads();
+    // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha)
+    {
+      const float denL = block_read<NT>(sm.redf[1]) + p.alpha;
+      float sl = 0.f;
+      for (int base = 0; base < nA * Gr; base += NT) {
+        const int q = base + t;
+        const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
+        const int s0 = k * Lr;
+        float acc = 0.f;
+        if constexpr (TAB) {
+          const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
+          for (int s = s0; s < s0 + Lr; s += 4) {
+            const v4u xv = *reinterpret_cast<const v4u*>(&sm.wc[s]);
+            const uint32_t cls4 = s < nBp ? trow[s >> 2] : 0u;
+            acc = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], acc);
+            acc = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], acc);
+          }
+        } else {
+          const int a = sm.A[o];
+          for (int s = s0; s < s0 + Lr; ++s)
+            acc = fmaf(sm.wc[s], sm.rho[class_of<BINS>(a, sm.B[min(s, nB - 1)])], acc);
+        }
+        for (int w = Gr >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
+        if (k == 0 && q / Gr < nA) {
+          const float ln = (sm.lc[o] * acc + p.alpha * sm.sc[o]) / denL;
+          sm.l2c[o] = ln;
+          sl += ln;
+        }
+      }
+      wave_partial<NT>(sl, sm.redf[3]);
+    }
+    __syncthreads();
+    // Eqs. (15), (14): rescale to unit mass
+    {
+      const float sumL = block_read<NT>(sm.redf[3]);
+      const float sumR = block_read<NT>(sm.redf[2]);
+      for (int i = t; i < nA; i += NT) sm.lc[i] = sm.l2c[i] / sumL;
+      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;
+    }
+    __syncthreads();
+  }
 }
 
 // Alg. 1 (Eqs. 11-15) for p.iters passes and the target histogram of
-// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); lists:
-// 3*BINS*BINS words of global scratch.  Writes illum/refl/target (counts)
-// if the pointers are non-null, and the target into `target_lds` (counts).
-template <int BINS, int NT>
+// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); gcells:
+// global scratch (gcap cells) for the class list when it does not fit in
+// LDS.  Writes
+// illum/refl/target (counts, dense over the l levels) when non-null.
+template <int BINS, int NT, int BUDGET>
 __device__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
-                            SolveSmem<BINS, NT>& sm, uint32_t* lists, float* illum, float* refl,
-                            float* target, float* target_lds, uint32_t* flags) {
+                            SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
+                            float* illum, float* refl, float* target, uint32_t* flags) {
   const int t = threadIdx.x;
-  // histograms -> probability units; occupied levels
   uint64_t ms = 0, mg = 0;
   for (int k = t; k < BINS; k += NT) {
     ms += hS[k];
@@ -696,112 +1048,105 @@ __device__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix
   const uint64_t Ns = block_sum<NT>(ms, sm.redu);
   const uint64_t Ng = block_sum<NT>(mg, sm.redu);
   if (t == 0 && (Ns != (uint64_t)npix || Ng != Ns)) atomicOr(flags, FLAG_HIST_MASS);
+  for (int k = t; k < BINS + 1; k += NT) sm.PA[k] = (k < BINS && hS[k]) ? 1 : 0;
+  __syncthreads();
+  const int nA = block_scan<NT, int32_t>(sm.PA, BINS + 1, sm.redi);
   const double invS = 1.0 / (double)Ns, invG = 1.0 / (double)Ng;
   for (int k = t; k < BINS; k += NT) {
     const float sv = (float)((double)hS[k] * invS);
-    const float gv = (float)((double)hG[k] * invG);
-    sm.s[k] = sv;
-    sm.g[k] = gv;
-    sm.lv[k] = sv;  // L(0) = H_C(S)
-    sm.rv[k] = gv;  // R(0) = H_C(grad S)
-    sm.off[0][k] = sv > 0.f ? 1 : 0;
-    sm.off[1][k] = gv > 0.f ? 1 : 0;
+    sm.sd[k] = sv;
+    if (hS[k]) {
+      const int i = sm.PA[k];
+      sm.A[i] = (uint16_t)k;
+      sm.sc[i] = sv;
+    }
   }
+  for (int k = t; k < BINS + 1; k += NT) sm.PB[k] = (k < BINS && hG[k]) ? 1 : 0;
   __syncthreads();
-  const int nA = block_scan<NT, int32_t>(sm.off[0], BINS, sm.redi);
-  const int nB = block_scan<NT, int32_t>(sm.off[1], BINS, sm.redi);
+  const int nB = block_scan<NT, int32_t>(sm.PB, BINS + 1, sm.redi);
   for (int k = t; k < BINS; k += NT) {
-    if (sm.s[k] > 0.f) sm.A[sm.off[0][k]] = (uint16_t)k;
-    if (sm.g[k] > 0.f) sm.B[sm.off[1][k]] = (uint16_t)k;
+    if (hG[k]) {
+      const int j = sm.PB[k];
+      sm.B[j] = (uint16_t)k;
+      sm.gc[j] = (float)((double)hG[k] * invG);
+    }
   }
   if (t == 0) {
     sm.nA = nA;
     sm.nB = nB;
   }
   __syncthreads();
-  build_lists<BINS, NT>(sm, lists);
-  const int nc = sm.nc;
-  const uint32_t* Lr = lists;
-  const uint32_t* Lc = lists + BINS * BINS;
-  const uint32_t* Lm = lists + 2 * BINS * BINS;
-
-  for (int it = 0; it < p.iters; ++it) {
-    // Eqs. (8), (11): class totals d_m and rho_m = s_m / d_m (K_ab s_index = L_a R_b rho)
-    seg_sweep<BINS, NT>(Lm, nc, sm.C[2], sm.off[2], sm.lv, sm.rv, sm.acc, sm.first_sum, sm.last_sum);
-    float ql = 0.f;
-    for (int k = t; k < BINS; k += NT) {
-      const float d = sm.acc[k];
-      sm.rho[k] = (d > 0.f && sm.s[k] > 0.f) ? sm.s[k] / d : 0.f;
-      const float l = sm.lv[k];
-      sm.u.it.l2[k] = l * l;
-      ql += l * l;
-    }
-    const float sumL2 = block_sum<NT>(ql, sm.redf);  // includes the barrier
-    // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta)
-    seg_sweep<BINS, NT>(Lc, nc, sm.C[1], sm.off[1], sm.u.it.l2, sm.rho, sm.acc, sm.first_sum, sm.last_sum);
-    const float denR = sumL2 + p.beta;
-    float qr = 0.f;
-    for (int k = t; k < BINS; k += NT) {
-      const float r = sm.rv[k];
-      const float rn = (r * sm.acc[k] + p.beta * sm.g[k]) / denR;
-      sm.rn[k] = rn;
-      sm.u.it.w[k] = rn * r;
-      qr += rn * rn;
-    }
-    const float sumR2 = block_sum<NT>(qr, sm.redf);
-    // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha)
-    seg_sweep<BINS, NT>(Lr, nc, sm.C[0], sm.off[0], sm.u.it.w, sm.rho, sm.acc, sm.first_sum, sm.last_sum);
-    const float denL = sumR2 + p.alpha;
-    float sl = 0.f, sr = 0.f;
-    for (int k = t; k < BINS; k += NT) {
-      const float ln = (sm.lv[k] * sm.acc[k] + p.alpha * sm.s[k]) / denL;
-      sm.u.it.l2[k] = ln;
-      sl += ln;
-      sr += sm.rn[k];
-    }
-    const float sumL = block_sum<NT>(sl, sm.redf);
-    const float sumR = block_sum<NT>(sr, sm.redf);
-    // Eqs. (15), (14): rescale to unit mass
-    for (int k = t; k < BINS; k += NT) {
-      sm.lv[k] = sm.u.it.l2[k] / sumL;
-      sm.rv[k] = sm.rn[k] / sumR;
+  for (int i = t; i < nA; i += NT) {
+    sm.inv2a[i] = sm.A[i] ? 1.f / (float)(2 * sm.A[i]) : 0.f;
+    sm.lc[i] = sm.sc[i];  // L(0) = H_C(S)
+  }
+  for (int j = t; j < nB; j += NT) sm.rc[j] = sm.gc[j];  // R(0) = H_C(grad S)
+  __syncthreads();
+  if constexpr (BINS == 256) {
+    build_class_list<BINS, NT, BUDGET>(sm, gcells, gcap);
+    if (!sm.use_list)
+      iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p);
+    else if (!sm.cells_lds)
+      iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p);
+    else if (sm.tab_lds)
+      iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p);
+    else
+      iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p);
+  } else {
+    if (t == 0) {
+      sm.C = 0;
+      sm.CS = 0;
+      sm.R = 0;
+      sm.nAp = (nA + 3) & ~3;
+      sm.nBp = (nB + 3) & ~3;
     }
     __syncthreads();
+    iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p);
   }
 
   // Eqs. (17)-(20): target_k = N * sum over cells with round(theta_a * b) = k
   // of L_a R_b.  Products of two floats are exact in FP64; they are summed in
   // 2^-62 fixed point, so the result does not depend on the order.
-  for (int k = t; k < BINS; k += NT) sm.u.tacc[k] = 0ull;
-  __syncthreads();
+  unsigned long long* tacc = reinterpret_cast<unsigned long long*>(sm.spare);  // BINS x u64
+  double* theta = reinterpret_cast<double*>(sm.spare) + BINS;                 // BINS doubles
+  for (int k = t; k < BINS; k += NT) tacc[k] = 0ull;
   for (int i = t; i < nA; i += NT) {
     const int a = sm.A[i];
-    const double theta = a ? pow((double)a / (double)(BINS - 1), p.inv_gamma) : 0.0;
-    const double la = (double)sm.lv[a];
+    theta[i] = a ? pow((double)a / (double)(BINS - 1), p.inv_gamma) : 0.0;  // Eq. (17)
+  }
+  __syncthreads();
+  constexpr int JC = 8;  // columns per work item
+  const int nJC = (nB + JC - 1) / JC;
+  for (int q = t; q < nA * nJC; q += NT) {
+    const int i = q / nJC, j0 = (q - (q / nJC) * nJC) * JC, j1 = min(j0 + JC, nB);
+    const double th = theta[i];
+    const double la = (double)sm.lc[i];
     int cur = -1;
     unsigned long long run = 0;
-    for (int j = 0; j < nB; ++j) {
-      const int b = sm.B[j];
-      const int k = (int)floor(theta * (double)b + 0.5);
-      const unsigned long long q = __double2ull_rn(la * (double)sm.rv[b] * 0x1p62);
+    for (int j = j0; j < j1; ++j) {
+      const int k = (int)floor(th * (double)sm.B[j] + 0.5);  // Eq. (19)
+      const unsigned long long qv = __double2ull_rn(la * (double)sm.rc[j] * 0x1p62);
       if (k != cur) {
-        if (cur >= 0 && run) atomicAdd(&sm.u.tacc[cur], run);
+        if (cur >= 0 && run) atomicAdd(&tacc[cur], run);
         cur = k;
         run = 0;
       }
-      run += q;
+      run += qv;
     }
-    if (cur >= 0 && run) atomicAdd(&sm.u.tacc[cur], run);
+    if (cur >= 0 && run) atomicAdd(&tacc[cur], run);
   }
   __syncthreads();
   const double Nd = (double)Ns;
   for (int k = t; k < BINS; k += NT) {
-    const float tv = (float)(Nd * ((double)sm.u.tacc[k] * 0x1p-62));
-    if (target_lds) target_lds[k] = tv;
-    if (target) target[k] = tv;
-    if (illum) illum[k] = (float)(Nd * (double)sm.lv[k]);
-    if (refl) refl[k] = (float)(Nd * (double)sm.rv[k]);
+    if (target) target[k] = (float)(Nd * ((double)tacc[k] * 0x1p-62));
+    if (illum) illum[k] = 0.f;
+    if (refl) refl[k] = 0.f;
   }
+  __syncthreads();
+  for (int i = t; i < nA; i += NT)
+    if (illum) illum[sm.A[i]] = (float)(Nd * (double)sm.lc[i]);
+  for (int j = t; j < nB; j += NT)
+    if (refl) refl[sm.B[j]] = (float)(Nd * (double)sm.rc[j]);
   __syncthreads();
 }
 

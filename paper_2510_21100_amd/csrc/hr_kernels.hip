@@ -27,7 +27,7 @@ template <int BITS>
 __global__ __launch_bounds__(NT_PIX) void k_hist(ImgDesc d, int64_t tile_px, uint32_t* hs, uint32_t* graw,
                                                  uint32_t* hg, uint32_t* ticket, uint32_t* flags) {
   constexpr int BINS = Cfg<BITS>::BINS;
-  __shared__ HistSmem<BITS> sm;
+  __shared__ HistSmem<BITS, NT_PIX> sm;
   __shared__ uint32_t red[NT_PIX / 64];
   __shared__ uint32_t last;
   const int64_t P0 = (int64_t)blockIdx.x * tile_px;
@@ -45,12 +45,29 @@ __global__ __launch_bounds__(NT_PIX) void k_hist(ImgDesc d, int64_t tile_px, uin
   if (threadIdx.x == 0) *ticket = 0;  // ready for the next call
 }
 
+// LDS budgets of the solver: the one-image kernel may take most of a CU's
+// 160 KB; inside the batched kernel the solver shares the union with the
+// pixel-tile state and stays small enough for several workgroups per CU.
+constexpr int SOLVE_BUDGET_PLAIN = 150 * 1024;
+// solver scratch per image in global memory (32-bit words), as allocated by
+// the workspace: 3 * l^2
+template <int BINS> constexpr int64_t LIST_WORDS = 3LL * BINS * BINS;
+constexpr int NT_SOLVE = 512;  // solver workgroup (one-image and batched kernels alike)
+constexpr int NT_BATCH = NT_SOLVE;
+// The batched kernel's register use allows one 512-thread workgroup per CU,
+// so its solver can take most of the CU's LDS as well.
+template <int BITS> struct BatchBudget {
+  static constexpr int value = 150 * 1024;
+};
+
 template <int BINS, int NT>
 __global__ __launch_bounds__(NT) void k_solve(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
                                               uint32_t* lists, float* illum, float* refl, float* target,
                                               uint32_t* flags) {
-  __shared__ SolveSmem<BINS, NT> sm;
-  solve_image<BINS, NT>(hS, hG, npix, p, sm, lists, illum, refl, target, nullptr, flags);
+  __shared__ SolveSmem<BINS, NT, SOLVE_BUDGET_PLAIN> sm;
+  solve_image<BINS, NT, SOLVE_BUDGET_PLAIN>(
+      hS, hG, npix, p, sm, reinterpret_cast<typename CellT<BINS>::type*>(lists),
+      (int64_t)LIST_WORDS<BINS> * 4 / (int64_t)sizeof(typename CellT<BINS>::type), illum, refl, target, flags);
 }
 
 template <int BINS, int NT>
@@ -81,9 +98,9 @@ __global__ __launch_bounds__(NT_PIX) void k_remap(ImgDesc d, int64_t tile_px, co
 
 template <int BITS>
 union BatchSmem {
-  HistSmem<BITS> hist;
-  SolveSmem<Cfg<BITS>::BINS, NT_PIX> solve;
-  LutSmem<Cfg<BITS>::BINS, NT_PIX> lut;
+  HistSmem<BITS, NT_BATCH> hist;
+  SolveSmem<Cfg<BITS>::BINS, NT_BATCH, BatchBudget<BITS>::value> solve;
+  LutSmem<Cfg<BITS>::BINS, NT_BATCH> lut;
   uint2 tab[Cfg<BITS>::BINS];
 };
 
@@ -97,98 +114,139 @@ __global__ void k_batch_reset(BatchHeader* hdr, ImageState* st, int bins) {
   if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next = 0;
 }
 
-// image owning batch tile `tile` (tile0 ascending over the descriptor table)
-__device__ inline int image_of_tile(const ImgDesc* desc, int n, int tile) {
+
+// Completes image i once all its histogram items are merged: adds up the
+// partial histograms, rebins the gradient histogram, runs the solver and the
+// LUT, then publishes the LUT.  Everything it needs is re-read from the
+// tables, so nothing of the item loop stays live across the solver.
+template <int BITS>
+__device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageState* s, int i,
+                             uint32_t* lists_base, int64_t lists_stride, uint32_t* flags, BatchSmem<BITS>& sm,
+                             uint32_t* red) {
+  constexpr int BINS = Cfg<BITS>::BINS;
+  uint32_t* hs = s->hs();
+  uint32_t* graw = s->graw(BINS);
+  uint32_t* hg = s->hg(BINS);
+  for (int k = threadIdx.x; k < 3 * BINS; k += NT_BATCH) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < ImageState::NSLOT; ++q)
+      v += __hip_atomic_load(s->slot(BINS, q) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (k < BINS) hs[k] = v;
+    else if (k < 3 * BINS - 1) graw[k - BINS] = v;
+  }
+  __threadfence();
+  __syncthreads();
+  rebin_gradient<BINS, NT_BATCH>(graw, hg, reinterpret_cast<uint32_t*>(&sm), red);
+  __threadfence();
+  __syncthreads();
+  __threadfence();
+  const int64_t npix = desc[i].npix;
+  const int slot = desc[i].slot;
+  const BatchOut out = hdr->out;
+  float* tgt = s->target(BINS);
+  solve_image<BINS, NT_BATCH, BatchBudget<BITS>::value>(
+      hs, hg, npix, hdr->params, sm.solve,
+      reinterpret_cast<typename CellT<BINS>::type*>(lists_base + (int64_t)i * lists_stride),
+      lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),
+      out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
+      tgt, flags);
+  __threadfence();
+  __syncthreads();
+  __threadfence();
+  uint16_t* lut = s->lut(BINS);
+  build_lut<BINS, NT_BATCH>(hs, tgt, sm.lut, lut);
+  __syncthreads();
+  if (out.target || out.luts) {
+    for (int k = threadIdx.x; k < BINS; k += NT_BATCH) {
+      if (out.target) out.target[(int64_t)slot * BINS + k] = tgt[k];
+      if (out.luts) out.luts[(int64_t)slot * BINS + k] = lut[k];
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&s->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// image owning item `it` of a range [first[i], first[i] + count[i]) per image
+// (first ascending over the descriptor table)
+template <bool REMAP>
+__device__ inline int image_of_item(const ImgDesc* desc, int n, int it) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    if ((REMAP ? desc[mid].rtile0 : desc[mid].tile0) <= it) lo = mid; else hi = mid - 1;
   }
   return lo;
 }
 
 template <int BITS>
-__global__ __launch_bounds__(NT_PIX) void k_batch(BatchHeader* hdr, const ImgDesc* desc, ImageState* st,
-                                                  uint32_t* lists_base, int64_t lists_stride, uint32_t* flags) {
+__global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgDesc* desc, ImageState* st,
+                                                    uint32_t* lists_base, int64_t lists_stride, uint32_t* flags) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ BatchSmem<BITS> sm;
-  __shared__ uint32_t red[NT_PIX / 64];
+  __shared__ uint32_t red[NT_BATCH / 64];
   __shared__ int item_s;
   __shared__ uint32_t last_s;
-  const int n = hdr->n;
-  const int ht = hdr->total_tiles;
-  const int64_t tile_px = hdr->tile_px;
-  const SolveParams p = hdr->params;
-  const BatchOut out = hdr->out;
   const int64_t st_words = ImageState::words(BINS);
+  int tab_img = -1;  // image whose remap table is in LDS
   for (;;) {
     if (threadIdx.x == 0) item_s = (int)atomicAdd(&hdr->next, 1u);
     __syncthreads();
     const int item = item_s;
     __syncthreads();
-    if (item >= 2 * ht) break;
+    const int ht = hdr->total_tiles;
+    if (item >= ht + hdr->total_rtiles) break;
     const bool is_hist = item < ht;
     const int tile = is_hist ? item : item - ht;
-    const int i = image_of_tile(desc, n, tile);
-    const ImgDesc d = desc[i];
+    const int i = is_hist ? image_of_item<false>(desc, hdr->n, tile) : image_of_item<true>(desc, hdr->n, tile);
     ImageState* s = reinterpret_cast<ImageState*>(reinterpret_cast<uint32_t*>(st) + i * st_words);
-    uint32_t* hs = s->hs();
-    uint32_t* graw = s->graw(BINS);
-    const int64_t P0 = (int64_t)(tile - d.tile0) * tile_px;
-    const int64_t P1 = min(P0 + tile_px, d.npix);
-    if (is_hist) {
-      hist_tile<BITS, NT_PIX>(d, P0, P1, sm.hist, hs, graw);
-      if (threadIdx.x == 0) {
-        if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
-        __threadfence();
-        last_s = (atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1) ? 1u : 0u;
-      }
-      __syncthreads();
-      if (last_s) {
-        __threadfence();
-        uint32_t* hg = s->hg(BINS);
-        rebin_gradient<BINS, NT_PIX>(graw, hg, reinterpret_cast<uint32_t*>(&sm), red);
-        __threadfence();
-        __syncthreads();
-        __threadfence();
-        float* tgt = s->target(BINS);
-        solve_image<BINS, NT_PIX>(hs, hg, d.npix, p, sm.solve, lists_base + (int64_t)i * lists_stride,
-                                  out.illum ? out.illum + (int64_t)d.slot * BINS : nullptr,
-                                  out.refl ? out.refl + (int64_t)d.slot * BINS : nullptr, tgt, nullptr,
-                                  flags);
-        __threadfence();
-        __syncthreads();
-        __threadfence();
-        uint16_t* lut = s->lut(BINS);
-        build_lut<BINS, NT_PIX>(hs, tgt, sm.lut, lut);
-        __syncthreads();
-        if (out.target || out.luts) {
-          for (int k = threadIdx.x; k < BINS; k += NT_PIX) {
-            if (out.target) out.target[(int64_t)d.slot * BINS + k] = tgt[k];
-            if (out.luts) out.luts[(int64_t)d.slot * BINS + k] = lut[k];
-          }
+    {
+      const ImgDesc d = desc[i];
+      if (is_hist) {
+        const int64_t tile_px = hdr->tile_px;
+        const int local = tile - d.tile0;
+        const int64_t P0 = (int64_t)local * tile_px;
+        const int64_t P1 = min(P0 + tile_px, d.npix);
+        uint32_t* part = s->slot(BINS, local % ImageState::NSLOT);
+        hist_tile<BITS, NT_BATCH>(d, P0, P1, sm.hist, part, part + BINS);
+        tab_img = -1;
+        if (threadIdx.x == 0) {
+          if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
+          __threadfence();
+          last_s = (atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1) ? 1u : 0u;
         }
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_store(&s->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (tab_img != i) {
+          if (threadIdx.x == 0) {
+            while (__hip_atomic_load(&s->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+              __builtin_amdgcn_s_sleep(2);
+          }
+          __syncthreads();
+          __threadfence();
+          const uint16_t* lut = s->lut(BINS);
+          for (int v = threadIdx.x; v < BINS; v += NT_BATCH) {
+            const uint32_t L = __hip_atomic_load(reinterpret_cast<const uint32_t*>(lut) + (v >> 1),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
+            const uint32_t m = v ? (uint32_t)((0xffffffffull + 2ull * v) / (2ull * v)) : 0u;
+            sm.tab[v] = make_uint2(m, lv);
+          }
+          __syncthreads();
+          tab_img = i;
+        }
+        const int64_t rtile_px = hdr->rtile_px;
+        const int64_t P0 = (int64_t)(tile - d.rtile0) * rtile_px;
+        const int64_t P1 = min(P0 + rtile_px, d.npix);
+        remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
+        if (threadIdx.x == 0) last_s = 0;
       }
-    } else {
-      if (threadIdx.x == 0) {
-        while (__hip_atomic_load(&s->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-          __builtin_amdgcn_s_sleep(2);
-      }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (last_s) {
       __threadfence();
-      const uint16_t* lut = s->lut(BINS);
-      for (int v = threadIdx.x; v < BINS; v += NT_PIX) {
-        const uint32_t L = __hip_atomic_load(reinterpret_cast<const uint32_t*>(lut) + (v >> 1), __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
-        const uint32_t m = v ? (uint32_t)((0xffffffffull + 2ull * v) / (2ull * v)) : 0u;
-        sm.tab[v] = make_uint2(m, lv);
-      }
-      __syncthreads();
-      remap_tile<BITS, NT_PIX>(d, P0, P1, sm.tab);
+      finish_image<BITS>(hdr, desc, s, i, lists_base, lists_stride, flags, sm, red);
+      tab_img = -1;
     }
     __syncthreads();
   }
@@ -223,11 +281,11 @@ hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix,
                  uint32_t* lists, float* illum, float* refl, float* target, uint32_t* flags, hipStream_t s) {
   // same workgroup shape as the batched kernel's solver: identical results
   if (bins == 256)
-    hipLaunchKernelGGL((k_solve<256, NT_PIX>), dim3(1), dim3(NT_PIX), 0, s, hS, hG, npix, p, lists, illum, refl,
-                       target, flags);
+    hipLaunchKernelGGL((k_solve<256, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
+                       refl, target, flags);
   else
-    hipLaunchKernelGGL((k_solve<1024, NT_PIX>), dim3(1), dim3(NT_PIX), 0, s, hS, hG, npix, p, lists, illum, refl,
-                       target, flags);
+    hipLaunchKernelGGL((k_solve<1024, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
+                       refl, target, flags);
   return hipGetLastError();
 }
 
@@ -259,16 +317,15 @@ hipError_t batch_reset(BatchHeader* hdr, ImageState* st, int bins, hipStream_t s
 hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImageState* st, uint32_t* lists,
                  int64_t lists_stride, uint32_t* flags, hipStream_t s) {
   if (bits == 8)
-    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_PIX), 0, s, hdr, desc, st, lists, lists_stride, flags);
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, st, lists, lists_stride, flags);
   else
-    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_PIX), 0, s, hdr, desc, st, lists, lists_stride, flags);
+    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, st, lists, lists_stride, flags);
   return hipGetLastError();
 }
 
-int step_px(int bits) { return NT_PIX * (bits == 8 ? Cfg<8>::PX : Cfg<10>::PX); }
-int max_width(int bits) {
-  return bits == 8 ? Cfg<8>::RING - 2 * NT_PIX * Cfg<8>::PX : Cfg<10>::RING - 2 * NT_PIX * Cfg<10>::PX;
-}
+int step_px(int bits) { return bits == 8 ? Pix<8, NT_PIX>::STEP : Pix<10, NT_PIX>::STEP; }
+int batch_step_px(int bits) { return bits == 8 ? Pix<8, NT_BATCH>::STEP : Pix<10, NT_BATCH>::STEP; }
+int max_width(int bits) { return bits == 8 ? MaxWidth<8>::value : MaxWidth<10>::value; }
 
 }  // namespace launch
 }  // namespace hr

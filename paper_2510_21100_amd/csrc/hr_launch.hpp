@@ -19,8 +19,10 @@ struct ImgDesc {
   int32_t H;
   int32_t in_vec;   // rows are tight and the base is 16-byte aligned
   int32_t out_vec;
-  int32_t ntiles;   // batched form: number of pixel tiles of this image
-  int32_t tile0;    // batched form: first tile of this image in the batch
+  int32_t ntiles;   // batched form: histogram items of this image
+  int32_t tile0;    // batched form: first histogram item of this image
+  int32_t rtiles;   // batched form: remap items of this image
+  int32_t rtile0;   // batched form: first remap item of this image
   int32_t slot;     // batched form: index of this image in the caller's arrays
   int32_t pad;
 };
@@ -48,24 +50,33 @@ struct BatchHeader {
   uint32_t next;         // work-queue cursor (reset on the device each call)
   uint32_t pad0;
   int32_t n;             // images in this call
-  int32_t total_tiles;   // histogram tiles (= remap tiles) over all images
-  int64_t tile_px;       // pixels per tile (multiple of the pixel step)
+  int32_t total_tiles;   // histogram items over all images
+  int32_t total_rtiles;  // remap items over all images
+  int32_t pad1;
+  int64_t tile_px;       // pixels per histogram item (multiple of the pixel step)
+  int64_t rtile_px;      // pixels per remap item (multiple of the pixel step)
   SolveParams params;
   BatchOut out;
 };
 
 // Per-image device state of the batched form, `words(bins)` 32-bit words.
+// Histogram items merge into one of NSLOT partial histograms (item mod
+// NSLOT), which spreads their atomics; the workgroup that merges the image's
+// last item adds the slots up in slot order.
 struct ImageState {
-  uint32_t done;   // histogram tiles merged so far
+  static constexpr int NSLOT = 8;
+  uint32_t done;   // histogram items merged so far
   uint32_t ready;  // LUT published
   uint32_t pad[2];
-  static constexpr int64_t words(int bins) { return 4 + 5 * (int64_t)bins + bins / 2; }
+  static constexpr int64_t words(int bins) { return 4 + 5 * (int64_t)bins + bins / 2 + NSLOT * 3LL * bins; }
   __host__ __device__ uint32_t* base() { return reinterpret_cast<uint32_t*>(this); }
   __host__ __device__ uint32_t* hs() { return base() + 4; }
   __host__ __device__ uint32_t* graw(int bins) { return base() + 4 + bins; }
   __host__ __device__ uint32_t* hg(int bins) { return base() + 4 + 3 * bins; }
   __host__ __device__ float* target(int bins) { return reinterpret_cast<float*>(base() + 4 + 4 * bins); }
   __host__ __device__ uint16_t* lut(int bins) { return reinterpret_cast<uint16_t*>(base() + 4 + 5 * bins); }
+  // partial histogram k: value histogram [bins] then raw gradient histogram [2 bins]
+  __host__ __device__ uint32_t* slot(int bins, int k) { return base() + 4 + 5 * bins + bins / 2 + k * 3 * bins; }
 };
 
 namespace launch {
@@ -81,6 +92,7 @@ hipError_t batch_reset(BatchHeader* hdr, ImageState* st, int bins, hipStream_t s
 hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImageState* st, uint32_t* lists,
                  int64_t lists_stride, uint32_t* flags, hipStream_t s);
 int step_px(int bits);
+int batch_step_px(int bits);
 int max_width(int bits);
 }  // namespace launch
 

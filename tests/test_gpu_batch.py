@@ -72,12 +72,12 @@ def test_batch_schedules_agree(H):
     ref, _ = H.enhance_batch(gimgs, H.Params(bins=256))
     torch.cuda.synchronize()
     ws = H.Workspace(max_images=8, max_bins=256)
-    for ts, wg in [(1, 1), (4, 3), (64, 2), (16, 4)]:
-        ws.set_schedule(ts, wg)
+    for ts, wg, rs in [(1, 1, 1), (4, 3, 64), (64, 2, 3), (16, 4, 8), (200, 1, 1)]:
+        ws.set_schedule(ts, wg, rs)
         outs, _ = H.enhance_batch(gimgs, H.Params(bins=256), ws=ws)
         torch.cuda.synchronize()
         for a, b in zip(outs, ref):
-            assert torch.equal(a, b), (ts, wg)
+            assert torch.equal(a, b), (ts, wg, rs)
     ws.close()
 
 

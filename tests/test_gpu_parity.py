@@ -30,7 +30,7 @@ def _hist_case(H, img, gpu_img=None):
     assert np.array_equal(to_np(hg).astype(np.int64), hG)
 
 
-HIST_SHAPES = [(256, 256), (664, 1000), (13, 31), (1, 37), (29, 1), (3, 5000), (2, 24576), (97, 4001)]
+HIST_SHAPES = [(256, 256), (664, 1000), (13, 31), (1, 37), (29, 1), (3, 5000), (2, 16384), (97, 4001)]
 
 
 @pytest.mark.parametrize("shape", HIST_SHAPES)
@@ -49,7 +49,7 @@ def test_hist_edge_images_10bit(H, name):
     _hist_case(H, edge_images(10)[name])
 
 
-@pytest.mark.parametrize("shape", [(300, 500), (17, 12288), (64, 2049)])
+@pytest.mark.parametrize("shape", [(300, 500), (17, 8192), (64, 2049)])
 def test_hist_bit_exact_10bit(H, shape):
     img = cfg_image(4, *shape, bits=10)
     _hist_case(H, img)
