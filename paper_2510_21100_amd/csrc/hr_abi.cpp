@@ -34,7 +34,7 @@ hr_status fail(hr_status s, const std::string& msg) {
 constexpr int kPlainTileSteps = 16;
 constexpr int kDefaultTileSteps = 32;
 constexpr int kDefaultWgPerCu = 1;
-constexpr int kDefaultRemapSteps = 8;
+constexpr int kDefaultRemapSteps = 16;
 constexpr int kStaging = 2;
 
 size_t table_bytes(int max_images) {

@@ -49,6 +49,19 @@ __device__ inline uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ inline uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
+// Cross-workgroup hand-off.  The release and acquire fences at agent scope
+// write back / invalidate the whole L2 of the XCD, so one wave issues them on
+// behalf of its workgroup: every wave first drains its own memory operations
+// (non-returning atomics included) and meets the others at a barrier, then a
+// single thread fences and signals; on the receiving side a single thread
+// observes the signal and fences before the barrier that releases the rest.
+__device__ inline void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ inline void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ inline void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// ceil(2^32 / (2v)) for v >= 1, as floor((2^32 - 1) / (2v)) + 1
+__device__ inline uint32_t recip_2v(uint32_t v) { return 0xffffffffu / (2u * v) + 1u; }
+
 // element k of a little-endian packed array of 8- or 16-bit lanes
 template <typename T, int N>
 __device__ inline uint32_t lane_of(const uint32_t (&w)[N], int k) {
@@ -401,9 +414,9 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
     for (int r = 0; r < REP; ++r) s += sm.hg[k * REP + r];
     if (s) atomicAdd(&g_graw[k], s);
   }
-  // every thread's merge is performed before any thread of the workgroup
-  // signals completion of the tile
-  __threadfence();
+  // every wave's merge atomics are performed before any thread of the
+  // workgroup signals completion of the tile
+  drain_memory();
   __syncthreads();
 }
 
@@ -500,8 +513,7 @@ __device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const uint2
 template <int BINS, int NT>
 __device__ inline void load_remap_table(const uint16_t* lut, uint2* tab) {
   for (int v = threadIdx.x; v < BINS; v += NT) {
-    const uint32_t m = v ? (uint32_t)((0xffffffffull + 2ull * v) / (2ull * v)) : 0u;  // ceil(2^32 / 2v)
-    tab[v] = make_uint2(m, (uint32_t)lut[v]);
+    tab[v] = make_uint2(v ? recip_2v(v) : 0u, (uint32_t)lut[v]);
   }
 }
 

@@ -35,12 +35,12 @@ __global__ __launch_bounds__(NT_PIX) void k_hist(ImgDesc d, int64_t tile_px, uin
   hist_tile<BITS, NT_PIX>(d, P0, P1, sm, hs, graw);
   if (threadIdx.x == 0) {
     if (sm.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
-    __threadfence();
+    fence_release_agent();
     last = (atomicAdd(ticket, 1u) == gridDim.x - 1) ? 1u : 0u;
+    if (last) fence_acquire_agent();
   }
   __syncthreads();
   if (!last) return;
-  __threadfence();
   rebin_gradient<BINS, NT_PIX>(graw, hg, sm.hs, red);
   if (threadIdx.x == 0) *ticket = 0;  // ready for the next call
 }
@@ -135,12 +135,11 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
     if (k < BINS) hs[k] = v;
     else if (k < 3 * BINS - 1) graw[k - BINS] = v;
   }
-  __threadfence();
+  drain_memory();
   __syncthreads();
   rebin_gradient<BINS, NT_BATCH>(graw, hg, reinterpret_cast<uint32_t*>(&sm), red);
-  __threadfence();
+  drain_memory();
   __syncthreads();
-  __threadfence();
   const int64_t npix = desc[i].npix;
   const int slot = desc[i].slot;
   const BatchOut out = hdr->out;
@@ -151,9 +150,8 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
       lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),
       out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
       tgt, flags);
-  __threadfence();
+  drain_memory();
   __syncthreads();
-  __threadfence();
   uint16_t* lut = s->lut(BINS);
   build_lut<BINS, NT_BATCH>(hs, tgt, sm.lut, lut);
   __syncthreads();
@@ -163,7 +161,7 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
       if (out.luts) out.luts[(int64_t)slot * BINS + k] = lut[k];
     }
   }
-  __threadfence();
+  drain_memory();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(&s->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -213,24 +211,25 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
         tab_img = -1;
         if (threadIdx.x == 0) {
           if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
-          __threadfence();
-          last_s = (atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1) ? 1u : 0u;
+          fence_release_agent();
+          const bool last = atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1;
+          if (last) fence_acquire_agent();
+          last_s = last ? 1u : 0u;
         }
       } else {
         if (tab_img != i) {
           if (threadIdx.x == 0) {
-            while (__hip_atomic_load(&s->ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+            while (__hip_atomic_load(&s->ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
               __builtin_amdgcn_s_sleep(2);
+            fence_acquire_agent();
           }
           __syncthreads();
-          __threadfence();
           const uint16_t* lut = s->lut(BINS);
           for (int v = threadIdx.x; v < BINS; v += NT_BATCH) {
             const uint32_t L = __hip_atomic_load(reinterpret_cast<const uint32_t*>(lut) + (v >> 1),
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
-            const uint32_t m = v ? (uint32_t)((0xffffffffull + 2ull * v) / (2ull * v)) : 0u;
-            sm.tab[v] = make_uint2(m, lv);
+            sm.tab[v] = make_uint2(v ? recip_2v(v) : 0u, lv);
           }
           __syncthreads();
           tab_img = i;
@@ -244,7 +243,6 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
     }
     __syncthreads();
     if (last_s) {
-      __threadfence();
       finish_image<BITS>(hdr, desc, s, i, lists_base, lists_stride, flags, sm, red);
       tab_img = -1;
     }
