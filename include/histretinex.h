@@ -79,8 +79,8 @@ typedef struct {
 } hr_params;
 
 /* Launch schedule of the batched form (chosen by the autotuner).  A step is
- * one pass of the persistent workgroup over its pixels: 512 threads x 16 px
- * (8-bit) or x 8 px (10-bit).
+ * one pass of the persistent workgroup over its pixels: 1024 threads x 8 px
+ * (8-bit) or x 4 px (10-bit).
  *  tile_steps  : steps per histogram work item
  *  wg_per_cu   : persistent workgroups per compute unit (1..8)
  *  remap_steps : steps per remap work item

@@ -31,11 +31,23 @@ hr_status fail(hr_status s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(HR_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kPlainTileSteps = 16;
+constexpr int kPlainTileSteps = 16;  // upper bound; small images take fewer
+constexpr int kPlainWgPerCu = 4;     // one-image kernels aim for this many tiles per CU
 constexpr int kDefaultTileSteps = 32;
 constexpr int kDefaultWgPerCu = 1;
 constexpr int kDefaultRemapSteps = 16;
 constexpr int kStaging = 2;
+
+// pixels per workgroup of the one-image kernels: at most kPlainTileSteps
+// steps, fewer when that leaves less than kPlainWgPerCu tiles per CU, but at
+// least min_steps (a histogram tile pays for clearing and merging its
+// private histograms)
+int64_t plain_tile_px(int bits, int64_t npix, int cu_count, int64_t min_steps) {
+  const int64_t step = hr::launch::step_px(bits);
+  const int64_t want = (int64_t)kPlainWgPerCu * std::max(cu_count, 1);
+  const int64_t steps = std::max<int64_t>(min_steps, std::min<int64_t>(kPlainTileSteps, npix / (want * step)));
+  return steps * step;
+}
 
 size_t table_bytes(int max_images) {
   return sizeof(hr::BatchHeader) + (size_t)max_images * sizeof(hr::ImgDesc);
@@ -265,7 +277,7 @@ hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uin
   uint32_t* graw = hist_grad_raw ? hist_grad_raw : ws->d_graw;
   HR_HIP(hr::launch::fill_u32(hist_v, bins, 0, s));
   HR_HIP(hr::launch::fill_u32(graw, 2 * bins - 1, 0, s));
-  const int64_t tile_px = (int64_t)kPlainTileSteps * hr::launch::step_px(bits);
+  const int64_t tile_px = plain_tile_px(bits, d.npix, ws->cu_count, 8);
   HR_HIP(hr::launch::hist(bits, d, tile_px, hist_v, graw, hist_grad, ws->d_flags + 1, ws->d_flags, s));
   return HR_OK;
 }
@@ -296,7 +308,7 @@ hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, con
   if ((st = check_ws(ws, bins))) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HR_HIP(hr::launch::lut(bins, hist_v, target, ws->d_lut, lut_out, s));
-  const int64_t tile_px = (int64_t)kPlainTileSteps * hr::launch::step_px(bits);
+  const int64_t tile_px = plain_tile_px(bits, d.npix, ws->cu_count, 1);
   HR_HIP(hr::launch::remap(bits, d, tile_px, ws->d_lut, s));
   return HR_OK;
 }

@@ -23,19 +23,25 @@ constexpr int NT_PIX = 256;  // threads of a pixel-streaming workgroup
 
 using v4u = uint32_t __attribute__((ext_vector_type(4)));
 using v2u = uint32_t __attribute__((ext_vector_type(2)));
+
+// Global-address-space view of a pointer known to point into device memory.
+// Accesses through a generic pointer become flat instructions, which hold the
+// LDS counter as well as the memory counter: every wait for an LDS result
+// would then also wait for the pixel loads in flight.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ inline gptr<T> to_global(T* p) { return (gptr<T>)p; }
 constexpr uint32_t FLAG_VALUE_CLAMPED = 1u;
 constexpr uint32_t FLAG_HIST_MASS = 2u;
 
-// Per bit depth: element type, levels and copies of each LDS histogram
-// (spreads same-level atomics over banks).
+// Per bit depth: element type and levels.
 template <int BITS> struct Cfg;
 template <> struct Cfg<8> {
   using pix_t = uint8_t;
-  static constexpr int BINS = 256, REP = 4;
+  static constexpr int BINS = 256;
 };
 template <> struct Cfg<10> {
   using pix_t = uint16_t;
-  static constexpr int BINS = 1024, REP = 1;
+  static constexpr int BINS = 1024;
 };
 
 
@@ -59,8 +65,15 @@ __device__ inline void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
 __device__ inline void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ inline void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// ceil(2^32 / (2v)) for v >= 1, as floor((2^32 - 1) / (2v)) + 1
-__device__ inline uint32_t recip_2v(uint32_t v) { return 0xffffffffu / (2u * v) + 1u; }
+// Workgroup barrier for the pixel loops.  __syncthreads() waits for every
+// outstanding LDS operation of the wave, the histogram atomics included; the
+// ring hand-off only needs the ring stores, so the loops wait for those
+// explicitly (lds_wait: LDS counter to zero, memory loads left in flight) and
+// then meet at a bare s_barrier while the atomics drain.  The asm's memory
+// clobber keeps the compiler from moving LDS accesses across it.
+__device__ inline void lds_wait() { __builtin_amdgcn_s_waitcnt(0xC07F); }  // lgkmcnt(0) only
+__device__ inline void bare_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
 
 // element k of a little-endian packed array of 8- or 16-bit lanes
 template <typename T, int N>
@@ -184,7 +197,7 @@ struct Pix {
 template <int NW, bool NONTEMPORAL>
 __device__ inline void load_words(const uint8_t* ptr, uint32_t (&w)[NW]) {
   if constexpr (NW == 12) {
-    const v4u* s = reinterpret_cast<const v4u*>(ptr);
+    const gptr<const v4u> s = to_global(reinterpret_cast<const v4u*>(ptr));
     v4u a, b, c;
     if (NONTEMPORAL) {
       a = __builtin_nontemporal_load(s);
@@ -200,7 +213,7 @@ __device__ inline void load_words(const uint8_t* ptr, uint32_t (&w)[NW]) {
     w[8] = c.x; w[9] = c.y; w[10] = c.z; w[11] = c.w;
   } else {
     static_assert(NW == 6, "chunk of 24 or 48 bytes");
-    const v2u* s = reinterpret_cast<const v2u*>(ptr);
+    const gptr<const v2u> s = to_global(reinterpret_cast<const v2u*>(ptr));
     v2u a, b, c;
     if (NONTEMPORAL) {
       a = __builtin_nontemporal_load(s);
@@ -218,12 +231,12 @@ __device__ inline void load_words(const uint8_t* ptr, uint32_t (&w)[NW]) {
 template <int NW>
 __device__ inline void store_words_nt(uint8_t* ptr, const uint32_t (&w)[NW]) {
   if constexpr (NW == 12) {
-    v4u* d = reinterpret_cast<v4u*>(ptr);
+    const gptr<v4u> d = to_global(reinterpret_cast<v4u*>(ptr));
     __builtin_nontemporal_store(v4u{w[0], w[1], w[2], w[3]}, d);
     __builtin_nontemporal_store(v4u{w[4], w[5], w[6], w[7]}, d + 1);
     __builtin_nontemporal_store(v4u{w[8], w[9], w[10], w[11]}, d + 2);
   } else {
-    v2u* d = reinterpret_cast<v2u*>(ptr);
+    const gptr<v2u> d = to_global(reinterpret_cast<v2u*>(ptr));
     __builtin_nontemporal_store(v2u{w[0], w[1]}, d);
     __builtin_nontemporal_store(v2u{w[2], w[3]}, d + 1);
     __builtin_nontemporal_store(v2u{w[4], w[5]}, d + 2);
@@ -257,7 +270,7 @@ __device__ inline void load_values(const ImgDesc& d, int64_t p, int n, uint32_t 
     for (int i = 0; i < PX; ++i) {
       uint32_t val = 0;
       if (i < n) {
-        const pix_t* px = reinterpret_cast<const pix_t*>(d.in + y * d.in_stride) + 3 * x;
+        const gptr<const pix_t> px = to_global(reinterpret_cast<const pix_t*>(d.in + y * d.in_stride)) + 3 * x;
         val = umax3(px[0], px[1], px[2]);
         if (BITS > 8 && val > TOP) {
           clamped = 1;
@@ -289,14 +302,21 @@ constexpr int pow2_at_least(int x) {
   return p;
 }
 
+// LDS of a histogram tile.  Each histogram has REP copies (thread t counts
+// into copy t mod REP, at word level * REP + t mod REP) so that lanes of a
+// wave hitting the same level mostly hit different words.  Low-light images
+// put most pixels in a few levels, so the workgroups that own a whole CU take
+// 16 copies.
 template <int BITS, int NT>
 struct HistSmem {
-  static constexpr int BINS = Cfg<BITS>::BINS, REP = Cfg<BITS>::REP;
+  static constexpr int BINS = Cfg<BITS>::BINS;
+  static constexpr int REP = BITS == 8 ? (NT >= 512 ? 16 : 4) : (NT >= 512 ? 4 : 1);
+  static constexpr int STRIDE = REP;
   static constexpr int RING = pow2_at_least(MaxWidth<BITS>::value + 2 * Pix<BITS, NT>::STEP);
   using pix_t = typename Cfg<BITS>::pix_t;
   static constexpr int RING_BYTES = RING * (int)sizeof(pix_t);
-  uint32_t hs[BINS * REP];
-  uint32_t hg[(2 * BINS - 1) * REP];
+  uint32_t hs[BINS * STRIDE];
+  uint32_t hg[(2 * BINS - 1) * STRIDE];
   uint32_t ring[RING_BYTES / 4 + 16];  // + 64-byte mirror of the start: no wrap on reads
   uint32_t clamped;
 };
@@ -321,54 +341,126 @@ __device__ inline void ring_write(uint32_t* ring, uint32_t byteoff, const uint32
   }
 }
 
-template <int BITS, int NT>
-__device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BITS, NT>& sm,
-                          uint32_t* __restrict__ g_hs, uint32_t* __restrict__ g_graw) {
+// element k (run-time index) of a packed lane array of 2 or 4 dwords,
+// through 64-bit shifts (no indexed register access)
+template <typename T, int N>
+__device__ inline uint32_t lane_dyn(const uint32_t (&w)[N], int k) {
+  static_assert(N == 2 || N == 4, "2 or 4 dwords");
+  constexpr int PER64 = 8 / (int)sizeof(T);
+  uint64_t sel = ((uint64_t)w[1] << 32) | w[0];
+  if constexpr (N == 4) {
+    const uint64_t hi = ((uint64_t)w[3] << 32) | w[2];
+    sel = k >= PER64 ? hi : sel;
+  }
+  const uint32_t x = (uint32_t)(sel >> ((k & (PER64 - 1)) * 8 * (int)sizeof(T)));
+  return sizeof(T) == 1 ? (x & 0xffu) : (x & 0xffffu);
+}
+
+// |a - b| + |c - b| for values below 2^16
+__device__ inline uint32_t grad_l1(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_sad_u16(a, b, __builtin_amdgcn_sad_u16(c, b, 0u));
+}
+
+// Chunks (PX pixels of one thread, NW dwords) kept in flight per thread by
+// the pixel loops: enough bytes per CU to cover the HBM latency.
+//
+// The loops overlap these loads with compute only if the compiler can count
+// them: a load skipped on some path leaves the count unknown and it then
+// waits for every outstanding load.  So the main loops run over steps in
+// which every thread has a full chunk (a condition uniform over the
+// workgroup) and issue their prefetches unconditionally, a prefetch that
+// would leave the range re-reading chunk 0 of the image instead (in bounds:
+// the vector paths require at least one full chunk).  Partial steps go to a
+// tail with the same arithmetic.
+constexpr int PREFETCH = 2;
+
+// V of the PX pixels of a chunk from its NW words
+template <int BITS, int PX, int NW>
+__device__ inline void values_of_words(const uint32_t (&w)[NW], uint32_t (&v)[PX], uint32_t& clamped) {
   using pix_t = typename Cfg<BITS>::pix_t;
-  constexpr int BINS = Cfg<BITS>::BINS, REP = Cfg<BITS>::REP;
-  constexpr int PX = Pix<BITS, NT>::PX, NV = Pix<BITS, NT>::NV, STEP = Pix<BITS, NT>::STEP;
-  constexpr int RING = HistSmem<BITS, NT>::RING;
-  constexpr int RING_BYTES = HistSmem<BITS, NT>::RING_BYTES;
-  constexpr int ESZ = (int)sizeof(pix_t);
-  const int t = threadIdx.x;
-  const int rep = t & (REP - 1);
-  const int64_t N = d.npix;
-  const int W = d.W;
-  const int64_t E = min(P1 + (int64_t)W, N);
+  constexpr uint32_t TOP = (1u << BITS) - 1;
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    uint32_t m = umax3(lane_of<pix_t>(w, 3 * i), lane_of<pix_t>(w, 3 * i + 1), lane_of<pix_t>(w, 3 * i + 2));
+    if (BITS > 8) {
+      clamped |= m > TOP ? 1u : 0u;
+      m = min(m, TOP);
+    }
+    v[i] = m;
+  }
+}
 
-  for (int i = t; i < BINS * REP; i += NT) sm.hs[i] = 0;
-  for (int i = t; i < (2 * BINS - 1) * REP; i += NT) sm.hg[i] = 0;
-  if (t == 0) sm.clamped = 0;
-  __syncthreads();
+template <int BITS, int NT>
+struct HistTile {
+  using pix_t = typename Cfg<BITS>::pix_t;
+  using SM = HistSmem<BITS, NT>;
+  static constexpr int BINS = Cfg<BITS>::BINS, REP = SM::REP, SD = SM::STRIDE;
+  static constexpr int PX = Pix<BITS, NT>::PX, NW = Pix<BITS, NT>::NW, NV = Pix<BITS, NT>::NV;
+  static constexpr int STEP = Pix<BITS, NT>::STEP;
+  static constexpr int RING = SM::RING, RING_BYTES = SM::RING_BYTES;
+  static constexpr int ESZ = (int)sizeof(pix_t);
+  static constexpr int64_t CB = 3 * ESZ;
 
+  const ImgDesc& d;
+  SM& sm;
+  const int64_t P0, P1, N, E;  // V is needed for [P0, E)
+  const int W, t, step_mod_w;
+  uint32_t* hs;  // this thread's copy: level k at hs[k * SD]
+  uint32_t* hg;
+  int x;  // column of this thread's gradient chunk
   uint32_t clamped = 0;
-  int64_t loaded = P0, done = P0;
-  while (done < P1) {
-    const int64_t dend = min(done + STEP, P1);
-    const int64_t need = min(dend - 1 + W, N - 1) + 1;
-    while (loaded < need) {
-      const int64_t p = loaded + (int64_t)t * PX;
-      const int n = (int)max((int64_t)0, min((int64_t)PX, E - p));
-      if (n > 0) {
-        uint32_t v[PX];
-        load_values<BITS, NT>(d, p, n, v, clamped);
-        uint32_t packed[NV];
+  int64_t loaded, done;
+
+  __device__ HistTile(const ImgDesc& d_, int64_t p0, int64_t p1, SM& sm_)
+      : d(d_), sm(sm_), P0(p0), P1(p1), N(d_.npix), E(min(p1 + (int64_t)d_.W, d_.npix)), W(d_.W),
+        t(threadIdx.x), step_mod_w(STEP % d_.W), hs(sm_.hs + (threadIdx.x & (REP - 1))),
+        hg(sm_.hg + (threadIdx.x & (REP - 1))), loaded(p0), done(p0) {
+    x = (int)((P0 + (int64_t)t * PX) % W);
+  }
+
+  // this thread's chunk of the load step starting at `at`, or chunk 0 when
+  // that one is not full
+  __device__ const uint8_t* chunk_or_first(int64_t at) const {
+    const int64_t p = at + (int64_t)t * PX;
+    return d.in + (p + PX <= E ? p : 0) * CB;
+  }
+
+  // V of the load step at `loaded` into the ring, V histogram of its pixels
+  // below P1.  `have`: the chunk's words are in w (else n < PX or strided).
+  __device__ void load_step(const uint32_t (&w)[NW], bool have) {
+    const int64_t p = loaded + (int64_t)t * PX;
+    const int n = (int)max((int64_t)0, min((int64_t)PX, E - p));
+    if (n > 0) {
+      uint32_t v[PX];
+      if (have) values_of_words<BITS, PX, NW>(w, v, clamped);
+      else load_values<BITS, NT>(d, p, n, v, clamped);
+      uint32_t packed[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) packed[k] = 0;
+      for (int q = 0; q < NV; ++q) packed[q] = 0;
 #pragma unroll
-        for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
-        const uint32_t boff = (uint32_t)(((p - P0) & (RING - 1)) * ESZ);
-        ring_write<NV>(sm.ring, boff, packed);
-        if (boff < 64) ring_write<NV>(sm.ring, RING_BYTES + boff, packed);
-        const int nh = (int)max((int64_t)0, min((int64_t)n, P1 - p));
+      for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
+      const uint32_t boff = (uint32_t)(((p - P0) & (RING - 1)) * ESZ);
+      ring_write<NV>(sm.ring, boff, packed);
+      if (boff < 64) ring_write<NV>(sm.ring, RING_BYTES + boff, packed);
+      lds_wait();  // the ring stores are done before this wave's barrier
+      const int64_t nh = P1 - p;  // pixels of the chunk inside the tile
+      if (nh >= PX) {
+#pragma unroll
+        for (int i = 0; i < PX; ++i) atomicAdd(&hs[v[i] * SD], 1u);
+      } else {
 #pragma unroll
         for (int i = 0; i < PX; ++i)
-          if (i < nh) atomicAdd(&sm.hs[v[i] * REP + rep], 1u);
+          if (i < nh) atomicAdd(&hs[v[i] * SD], 1u);
       }
-      loaded += STEP;
-      __syncthreads();
     }
-    // gradient of pixels [done, dend)
+  }
+
+  // gradient of pixels [done, dend) once the row below them is in the ring:
+  // right neighbour from the same chunk (or the next one), lower neighbour
+  // one row further on
+  __device__ void grad_step() {
+    const int64_t dend = min(done + STEP, P1);
+    if (min(dend - 1 + W, N - 1) + 1 > loaded) return;  // uniform
     const int64_t q = done + (int64_t)t * PX;
     const int n = (int)max((int64_t)0, min((int64_t)PX, dend - q));
     if (n > 0) {
@@ -376,43 +468,118 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
       uint32_t own[NV];
       ring_read<NV>(sm.ring, boff, own);  // aligned: the shift is 0
       const uint32_t rboff = boff + PX * ESZ;  // <= RING_BYTES: mirror covers it
-      const uint32_t right_last =
-          ESZ == 1 ? (uint32_t)reinterpret_cast<const uint8_t*>(sm.ring)[rboff]
-                   : (uint32_t)reinterpret_cast<const uint16_t*>(sm.ring)[rboff >> 1];
+      const uint32_t right_last = ESZ == 1 ? (uint32_t)reinterpret_cast<const uint8_t*>(sm.ring)[rboff]
+                                           : (uint32_t)reinterpret_cast<const uint16_t*>(sm.ring)[rboff >> 1];
       const uint32_t dboff = (uint32_t)(((q + W - P0) & (RING - 1)) * ESZ);
       uint32_t dn[NV];
       ring_read<NV>(sm.ring, dboff, dn);
-      int x = (int)(q % W);
+      if (n == PX && N - W - q >= PX && W > PX) {
+        // every pixel has a row below and at most one ends its row: count all
+        // with their right neighbour, then move the row-end pixel to its
+        // level without the horizontal term
 #pragma unroll
-      for (int i = 0; i < PX; ++i) {
-        if (i < n) {
-          const uint32_t v = lane_of<pix_t>(own, i);
+        for (int i = 0; i < PX; ++i) {
+          const uint32_t vv = lane_of<pix_t>(own, i);
           const uint32_t vr = (i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last;
-          const uint32_t vd = lane_of<pix_t>(dn, i);
-          uint32_t g = 0;
-          if (x + 1 < W) g += absdiff(vr, v);
-          if (q + i + W < N) g += absdiff(vd, v);
-          atomicAdd(&sm.hg[g * REP + rep], 1u);
-          if (++x == W) x = 0;
+          atomicAdd(&hg[grad_l1(vr, vv, lane_of<pix_t>(dn, i)) * SD], 1u);
+        }
+        const int e = W - 1 - x;
+        if (e < PX) {
+          const uint32_t ve = lane_dyn<pix_t>(own, e);
+          const uint32_t vre = (e + 1 < PX) ? lane_dyn<pix_t>(own, e + 1) : right_last;
+          const uint32_t vde = lane_dyn<pix_t>(dn, e);
+          atomicSub(&hg[grad_l1(vre, ve, vde) * SD], 1u);
+          atomicAdd(&hg[grad_l1(ve, ve, vde) * SD], 1u);
+        }
+      } else {
+        int xx = x;
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+          if (i < n) {
+            const uint32_t vv = lane_of<pix_t>(own, i);
+            const uint32_t vr = (xx + 1 < W) ? ((i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last) : vv;
+            const uint32_t vd = (q + i + W < N) ? lane_of<pix_t>(dn, i) : vv;
+            atomicAdd(&hg[grad_l1(vr, vv, vd) * SD], 1u);
+            if (++xx == W) xx = 0;
+          }
         }
       }
     }
+    x += step_mod_w;
+    if (x >= W) x -= W;
     done = dend;
-    __syncthreads();
   }
+
+  // one load step, then the gradient step if its rows are loaded; the
+  // barriers separate ring stores from ring reads and reads from the next
+  // step's stores
+  __device__ void step(const uint32_t (&w)[NW], bool have) {
+    load_step(w, have);
+    loaded += STEP;
+    bare_barrier();
+    grad_step();
+    bare_barrier();  // ring reads of this step have returned (their values are consumed)
+  }
+
+  __device__ void run() {
+    if (d.in_vec && N >= PX) {
+      uint32_t buf[PREFETCH][NW];
+#pragma unroll
+      for (int j = 0; j < PREFETCH; ++j) load_words<NW, false>(chunk_or_first(P0 + (int64_t)j * STEP), buf[j]);
+      // steps whose chunks are all full, PREFETCH at a time
+      while (loaded + (int64_t)PREFETCH * STEP <= E) {
+#pragma unroll
+        for (int k = 0; k < PREFETCH; ++k) {
+          step(buf[k], true);  // buf[k] is refilled once its words are consumed
+          load_words<NW, false>(chunk_or_first(loaded - STEP + (int64_t)PREFETCH * STEP), buf[k]);
+        }
+      }
+      // the rest: possibly partial or empty load steps
+      while (done < P1) {
+#pragma unroll
+        for (int k = 0; k < PREFETCH; ++k) {
+          if (done < P1) {
+            const int64_t p = loaded + (int64_t)t * PX;
+            step(buf[k], p + PX <= E);
+            load_words<NW, false>(chunk_or_first(loaded - STEP + (int64_t)PREFETCH * STEP), buf[k]);
+          }
+        }
+      }
+    } else {
+      uint32_t none[NW];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) none[q] = 0;
+      while (done < P1) step(none, false);
+    }
+  }
+};
+
+template <int BITS, int NT>
+__device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BITS, NT>& sm,
+                          uint32_t* __restrict__ g_hs, uint32_t* __restrict__ g_graw) {
+  using SM = HistSmem<BITS, NT>;
+  constexpr int BINS = Cfg<BITS>::BINS, REP = SM::REP, SD = SM::STRIDE;
+  const int t = threadIdx.x;
+  for (int i = t; i < BINS * SD; i += NT) sm.hs[i] = 0;
+  for (int i = t; i < (2 * BINS - 1) * SD; i += NT) sm.hg[i] = 0;
+  if (t == 0) sm.clamped = 0;
+  __syncthreads();
+  HistTile<BITS, NT> ht(d, P0, P1, sm);
+  ht.run();
+  const uint32_t clamped = ht.clamped;
   if (clamped) atomicOr(&sm.clamped, 1u);
   __syncthreads();
   for (int k = t; k < BINS; k += NT) {
     uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < REP; ++r) s += sm.hs[k * REP + r];
-    if (s) atomicAdd(&g_hs[k], s);
+    for (int r = 0; r < REP; ++r) s += sm.hs[k * SD + r];
+    if (s) __hip_atomic_fetch_add(to_global(g_hs) + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   for (int k = t; k < 2 * BINS - 1; k += NT) {
     uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < REP; ++r) s += sm.hg[k * REP + r];
-    if (s) atomicAdd(&g_graw[k], s);
+    for (int r = 0; r < REP; ++r) s += sm.hg[k * SD + r];
+    if (s) __hip_atomic_fetch_add(to_global(g_graw) + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // every wave's merge atomics are performed before any thread of the
   // workgroup signals completion of the tile
@@ -428,13 +595,13 @@ __device__ void rebin_gradient(const uint32_t* g_graw, uint32_t* g_hg, uint32_t*
   const int t = threadIdx.x;
   uint32_t gm = 0;
   for (int j = t; j < 2 * BINS - 1; j += NT) {
-    const uint32_t c = __hip_atomic_load(g_graw + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t c = __hip_atomic_load(to_global(g_graw) + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (c) gm = max(gm, (uint32_t)j);
   }
   for (int k = t; k < BINS; k += NT) tmp[k] = 0;
   const uint32_t gmax = block_max<NT>(gm, red);
   for (int j = t; j <= (int)gmax; j += NT) {
-    const uint32_t c = __hip_atomic_load(g_graw + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t c = __hip_atomic_load(to_global(g_graw) + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (c) {
       const uint32_t q = gmax ? (uint32_t)((2ull * (BINS - 1) * j + gmax) / (2ull * gmax)) : 0u;
       atomicAdd(&tmp[q], c);
@@ -445,76 +612,104 @@ __device__ void rebin_gradient(const uint32_t* g_graw, uint32_t* g_hg, uint32_t*
 }
 
 // ---------------------------------------------------------------------------
-// remap tile: out_c = round-half-up(c * LUT[V] / V), black -> LUT[0].
-// The division by 2V is a multiply-high by M[V] = ceil(2^32 / (2V)), exact for
-// every numerator 2cL + V < 2^32 / (2V - 1) (all 10-bit cases included).
-// `tab[v]` = {M[v], LUT[v]} in LDS.
+// remap tile: out_c = round-half-up(c * LUT[V] / V) = floor(t) with
+// t = (2 c LUT[V] + V) / (2V), black -> LUT[0].  Evaluated as
+// trunc(fma(c, ratio[V], bias[V])) from a table in LDS: for V >= 1 ratio is
+// LUT[V] / V rounded up to FP32 and bias = 1/2, so c * ratio + 1/2 exceeds t
+// by less than 1023 * 2^-23; t is a multiple of 1/(2V) >= 1/2046, hence the
+// rounded FMA stays in [floor(t), floor(t) + 1) and truncation is exact.  For
+// V = 0 every channel is 0, ratio = 0 and bias = LUT[0] + 1/2.
 // ---------------------------------------------------------------------------
 
+__device__ inline float2 remap_entry(uint32_t v, uint32_t L) {
+  if (v == 0) return make_float2(0.f, (float)L + 0.5f);
+  float r = (float)((double)L / (double)v);
+  if ((double)r * (double)v < (double)L) r = __uint_as_float(__float_as_uint(r) + 1u);
+  return make_float2(r, 0.5f);
+}
+
+template <int BITS, int PX, int NW>
+__device__ inline void remap_words(const uint32_t (&w)[NW], uint32_t (&o)[NW], const float2* tab) {
+  using pix_t = typename Cfg<BITS>::pix_t;
+  constexpr float TOPF = (float)((1u << BITS) - 1);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) o[k] = 0;
+#pragma unroll
+  for (int i = 0; i < PX; ++i) {
+    float r = (float)lane_of<pix_t>(w, 3 * i), g = (float)lane_of<pix_t>(w, 3 * i + 1),
+          b = (float)lane_of<pix_t>(w, 3 * i + 2);
+    if (BITS > 8) {
+      r = fminf(r, TOPF);
+      g = fminf(g, TOPF);
+      b = fminf(b, TOPF);
+    }
+    const float2 e = tab[(uint32_t)fmaxf(fmaxf(r, g), b)];
+    set_lane<pix_t>(o, 3 * i, (uint32_t)fmaf(r, e.x, e.y));
+    set_lane<pix_t>(o, 3 * i + 1, (uint32_t)fmaf(g, e.x, e.y));
+    set_lane<pix_t>(o, 3 * i + 2, (uint32_t)fmaf(b, e.x, e.y));
+  }
+}
+
+// n (< PX for a partial chunk) pixels from p, one at a time (any row stride)
 template <int BITS>
-__device__ inline uint32_t remap_channel(uint32_t c, uint32_t v, uint2 e) {
-  const uint32_t q = __umulhi(2u * c * e.y + v, e.x);
-  return v ? q : e.y;
+__device__ void remap_pixels(const ImgDesc& d, int64_t p, int n, const float2* tab) {
+  using pix_t = typename Cfg<BITS>::pix_t;
+  constexpr uint32_t TOP = (1u << BITS) - 1;
+  int64_t y = p / d.W;
+  int x = (int)(p - y * d.W);
+  for (int i = 0; i < n; ++i) {
+    const gptr<const pix_t> s = to_global(reinterpret_cast<const pix_t*>(d.in + y * d.in_stride)) + 3 * x;
+    const gptr<pix_t> o = to_global(reinterpret_cast<pix_t*>(d.out + y * d.out_stride)) + 3 * x;
+    const uint32_t r = min((uint32_t)s[0], TOP), g = min((uint32_t)s[1], TOP), bl = min((uint32_t)s[2], TOP);
+    const float2 e = tab[umax3(r, g, bl)];
+    o[0] = (pix_t)(uint32_t)fmaf((float)r, e.x, e.y);
+    o[1] = (pix_t)(uint32_t)fmaf((float)g, e.x, e.y);
+    o[2] = (pix_t)(uint32_t)fmaf((float)bl, e.x, e.y);
+    if (++x == d.W) {
+      x = 0;
+      ++y;
+    }
+  }
 }
 
 template <int BITS, int NT>
-__device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const uint2* tab) {
+__device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const float2* tab) {
   using pix_t = typename Cfg<BITS>::pix_t;
   constexpr int PX = Pix<BITS, NT>::PX, NW = Pix<BITS, NT>::NW, STEP = Pix<BITS, NT>::STEP;
-  constexpr uint32_t TOP = (1u << BITS) - 1;
-  for (int64_t p = P0 + (int64_t)threadIdx.x * PX; p < P1; p += STEP) {
-    const int n = (int)min((int64_t)PX, P1 - p);
-    if (d.in_vec && d.out_vec && n == PX) {
-      uint32_t w[NW];
-      load_words<NW, true>(d.in + p * 3 * (int64_t)sizeof(pix_t), w);
+  constexpr int64_t CB = 3 * (int64_t)sizeof(pix_t);
+  const bool vec = d.in_vec && d.out_vec;
+  // chunk j of this thread (pixels p0 + j STEP ..) lives in buf[j mod PREFETCH]
+  const int64_t p0 = P0 + (int64_t)threadIdx.x * PX;
+  uint32_t buf[PREFETCH][NW];
 #pragma unroll
-      for (int i = 0; i < PX; ++i) {
-        uint32_t r = lane_of<pix_t>(w, 3 * i), g = lane_of<pix_t>(w, 3 * i + 1),
-                 bl = lane_of<pix_t>(w, 3 * i + 2);
-        if (BITS > 8) {
-          r = min(r, TOP);
-          g = min(g, TOP);
-          bl = min(bl, TOP);
+  for (int j = 0; j < PREFETCH; ++j) {
+    const int64_t p = p0 + (int64_t)j * STEP;
+    if (vec && p + PX <= P1) load_words<NW, true>(d.in + p * CB, buf[j]);
+  }
+  for (int64_t p = p0; p < P1;) {
+#pragma unroll
+    for (int k = 0; k < PREFETCH; ++k) {
+      if (p < P1) {
+        const int n = (int)min((int64_t)PX, P1 - p);
+        if (vec && n == PX) {
+          uint32_t o[NW];
+          remap_words<BITS, PX, NW>(buf[k], o, tab);
+          const int64_t pf = p + (int64_t)PREFETCH * STEP;
+          if (pf + PX <= P1) load_words<NW, true>(d.in + pf * CB, buf[k]);
+          store_words_nt<NW>(d.out + p * CB, o);
+        } else {
+          remap_pixels<BITS>(d, p, n, tab);
         }
-        const uint32_t v = umax3(r, g, bl);
-        const uint2 e = tab[v];
-        set_lane<pix_t>(w, 3 * i, remap_channel<BITS>(r, v, e));
-        set_lane<pix_t>(w, 3 * i + 1, remap_channel<BITS>(g, v, e));
-        set_lane<pix_t>(w, 3 * i + 2, remap_channel<BITS>(bl, v, e));
-      }
-      store_words_nt<NW>(d.out + p * 3 * (int64_t)sizeof(pix_t), w);
-    } else {
-      int64_t y = p / d.W;
-      int x = (int)(p - y * d.W);
-      for (int i = 0; i < n; ++i) {
-        const pix_t* s = reinterpret_cast<const pix_t*>(d.in + y * d.in_stride) + 3 * x;
-        pix_t* o = reinterpret_cast<pix_t*>(d.out + y * d.out_stride) + 3 * x;
-        uint32_t r = s[0], g = s[1], bl = s[2];
-        if (BITS > 8) {
-          r = min(r, TOP);
-          g = min(g, TOP);
-          bl = min(bl, TOP);
-        }
-        const uint32_t v = umax3(r, g, bl);
-        const uint2 e = tab[v];
-        o[0] = (pix_t)remap_channel<BITS>(r, v, e);
-        o[1] = (pix_t)remap_channel<BITS>(g, v, e);
-        o[2] = (pix_t)remap_channel<BITS>(bl, v, e);
-        if (++x == d.W) {
-          x = 0;
-          ++y;
-        }
+        p += STEP;
       }
     }
   }
 }
 
-// Remap table {M[v], LUT[v]} from a LUT in global memory.
+// Remap table from a LUT in global memory.
 template <int BINS, int NT>
-__device__ inline void load_remap_table(const uint16_t* lut, uint2* tab) {
-  for (int v = threadIdx.x; v < BINS; v += NT) {
-    tab[v] = make_uint2(v ? recip_2v(v) : 0u, (uint32_t)lut[v]);
-  }
+__device__ inline void load_remap_table(const uint16_t* lut, float2* tab) {
+  for (int v = threadIdx.x; v < BINS; v += NT) tab[v] = remap_entry((uint32_t)v, (uint32_t)lut[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -739,7 +934,7 @@ __device__ inline uint8_t* class_table(SolveSmem<BINS, NT, BUDGET>& sm) {
 // class the cells are ordered by row slice, row and column.  Chunk u holds
 // its cells contiguously from u * CS.  256 levels only.
 template <int BINS, int NT, int BUDGET>
-__device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells,
+__device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells,
                                  int64_t gcap) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
@@ -776,11 +971,15 @@ __device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT
   mx = block_max<NT>(mx, sm.redi);
   const int nc = block_sum<NT>(tot, sm.redi);
   if (t < 64) {
-    // one wave lays the chunks out: class sizes in registers, the position
-    // carried as a wave-uniform scalar.  The chunk size starts at about one
-    // round of chunks and grows until the padded layout fits RMAX rounds; it
-    // fits at the latest when every class has one chunk (C >= mx): at most
-    // BINS chunks and no padding.
+    // one wave lays the chunks out, classes in order, each class's chunks
+    // inside one 64-chunk group: a class that would straddle a group
+    // boundary starts the next group.  Per block of 64 classes (one per
+    // lane) the positions are a prefix sum of the chunk counts; the first
+    // straddling class is moved to the next boundary and the scan repeated
+    // until none straddles, which is the sequential greedy result.  The
+    // chunk size starts at about one round of chunks and grows until the
+    // layout fits RMAX rounds; it fits at the latest when every class has one
+    // chunk (C >= mx): at most BINS chunks and no padding.
     constexpr int Q = (BINS + 63) / 64;
     const int lane = t;
     int cs[Q], offs[Q];
@@ -797,11 +996,23 @@ __device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int nv = (cs[q] + C - 1) / C;
-        for (int l = 0; l < 64; ++l) {
-          const int n = __builtin_amdgcn_readlane(nv, l);
-          if (n && (pos & 63) + n > 64) pos = (pos + 63) & ~63;
-          if (lane == l) offs[q] = pos;
-          pos += n;
+        int pad = 0;
+        for (int guard = 0; guard <= 64; ++guard) {
+          const int w = nv + pad;
+          int incl = w;
+#pragma unroll
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+          }
+          offs[q] = pos + incl - nv;  // start of this class after its padding
+          const bool straddle = nv > 0 && (offs[q] & 63) + nv > 64;
+          const uint64_t mask = __ballot(straddle);
+          if (!mask) {
+            pos += __shfl(incl, 63, 64);
+            break;
+          }
+          if (lane == (int)__builtin_ctzll(mask)) pad += 64 - (offs[q] & 63);
         }
       }
       if (pos <= RMAX * NT || C >= mx) break;
@@ -830,31 +1041,44 @@ __device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT
   const int C = sm.C, CS = sm.CS, R = sm.R;
   cell_t* cells = sm.cells_lds ? cell_store(sm) : gcells;
   const cell_t zero_cell = (cell_t)(nA | (nB << SH));  // lc[nA] = rc[nB] = 0
-  for (int q = t; q < R * NT * CS; q += NT) cells[q] = zero_cell;
   for (int m = t; m < BINS; m += NT) {
     const int c = sm.csz[m];
     for (int u = 0; u * C < c; ++u) sm.chunk_cls[sm.off[m] + u] = (int16_t)m;
   }
   __syncthreads();
-  for (int q = t; q < KS * BINS; q += NT) {
-    const int m = q % BINS, k = q / BINS;
-    if (!sm.cnt[k * BINS + m]) continue;
-    int c = 0;  // cells of class m in earlier slices
-    for (int kk = 0; kk < k; ++kk) c += sm.cnt[kk * BINS + m];
-    int chunk = sm.off[m] + c / C, slot = c - (c / C) * C;
-    const int r0 = sm.PA[m], nr = nA - r0;
-    const int i0 = r0 + (k * nr) / KS, i1 = r0 + ((k + 1) * nr) / KS;
-    for (int i = i0; i < i1; ++i) {
-      int jlo, jhi;
-      class_run<BINS>(sm, i, m, jlo, jhi);
-      for (int j = jlo; j < jhi; ++j) {
-        cells[chunk * CS + slot] = (cell_t)(i | (j << SH));
-        if (++slot == C) {
-          slot = 0;
-          ++chunk;
+  // one lane per chunk: the chunk's first cell is cell (u - off[m]) C of
+  // class m in row-major order; find its row slice from the slice counts,
+  // then its row, then write C cells along the class's row runs (a class's
+  // last chunk and the padding chunks are completed with zero cells)
+  for (int u = t; u < R * NT; u += NT) {
+    cell_t* cp = cells + (size_t)u * CS;
+    const int m = sm.chunk_cls[u];
+    int s = 0;
+    if (m >= 0) {
+      int r0 = (u - sm.off[m]) * C;
+      const int n = min(C, sm.csz[m] - r0);
+      int k = 0;
+      while (k < KS - 1 && r0 >= sm.cnt[k * BINS + m]) r0 -= sm.cnt[(k++) * BINS + m];
+      const int rb = sm.PA[m], nr = nA - rb;
+      int i = rb + (k * nr) / KS, jlo = 0, jhi = 0;
+      for (; i < nA; ++i) {
+        class_run<BINS>(sm, i, m, jlo, jhi);
+        if (r0 < jhi - jlo) break;
+        r0 -= jhi - jlo;
+      }
+      int j = jlo + r0;
+      for (; s < n && i < nA; ++s) {
+        cp[s] = (cell_t)(i | (j << SH));
+        if (++j >= jhi) {
+          do {
+            if (++i >= nA) break;
+            class_run<BINS>(sm, i, m, jlo, jhi);
+          } while (jhi <= jlo);
+          j = jlo;
         }
       }
     }
+    for (; s < C; ++s) cp[s] = zero_cell;
   }
   if (sm.tab_lds) {
     uint8_t* tab = class_table(sm);
@@ -876,7 +1100,7 @@ __device__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT
 // gathers over row runs); CELLS_LDS / TAB: where the list and the class
 // tables live, so that every access compiles to its address space.
 template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
-__device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
+__device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
                         const SolveParams& p) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
@@ -912,7 +1136,10 @@ __device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BI
         for (int r = 0; r < R; ++r) {
           const int u = r * NT + t;
           const cell_t* cp = cells + (size_t)u * CS;
-          float acc = 0.f;
+          // four independent partial sums (one per cell position mod 4) keep
+          // several gathers in flight; fixed order, so deterministic
+          float a4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
           for (int k = 0; k < C; k += 4) {
             uint32_t e[4];
             if constexpr (sizeof(cell_t) == 2) {
@@ -923,8 +1150,9 @@ __device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BI
               e[0] = w.x; e[1] = w.y; e[2] = w.z; e[3] = w.w;
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x) acc = fmaf(sm.lc[e[x] & MASK], sm.rc[e[x] >> SH], acc);
+            for (int x = 0; x < 4; ++x) a4[x] = fmaf(sm.lc[e[x] & MASK], sm.rc[e[x] >> SH], a4[x]);
           }
+          float acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
           const int cls = sm.chunk_cls[u];
           const int seg0 = cls >= 0 ? (sm.off[cls] & 63) : 64;  // lane of the class's first chunk
 #pragma unroll
@@ -970,14 +1198,17 @@ __device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BI
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
+          float a4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
           for (int s = s0; s < s0 + Lc; s += 4) {
             const v4u xv = *reinterpret_cast<const v4u*>(&sm.l2c[s]);
             const uint32_t cls4 = s < nAp ? trow[s >> 2] : 0u;
-            acc = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], acc);
+            a4[0] = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], a4[0]);
+            a4[1] = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], a4[1]);
+            a4[2] = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], a4[2]);
+            a4[3] = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], a4[3]);
           }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         } else {
           const int b = sm.B[o];
           for (int s = s0; s < s0 + Lc; ++s)
@@ -1008,14 +1239,17 @@ __device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BI
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
+          float a4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
           for (int s = s0; s < s0 + Lr; s += 4) {
             const v4u xv = *reinterpret_cast<const v4u*>(&sm.wc[s]);
             const uint32_t cls4 = s < nBp ? trow[s >> 2] : 0u;
-            acc = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], acc);
-            acc = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], acc);
+            a4[0] = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], a4[0]);
+            a4[1] = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], a4[1]);
+            a4[2] = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], a4[2]);
+            a4[3] = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], a4[3]);
           }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         } else {
           const int a = sm.A[o];
           for (int s = s0; s < s0 + Lr; ++s)
@@ -1048,7 +1282,7 @@ __device__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BI
 // LDS.  Writes
 // illum/refl/target (counts, dense over the l levels) when non-null.
 template <int BINS, int NT, int BUDGET>
-__device__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
+__device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
                             SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
                             float* illum, float* refl, float* target, uint32_t* flags) {
   const int t = threadIdx.x;

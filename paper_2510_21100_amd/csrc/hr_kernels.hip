@@ -52,7 +52,7 @@ constexpr int SOLVE_BUDGET_PLAIN = 150 * 1024;
 // solver scratch per image in global memory (32-bit words), as allocated by
 // the workspace: 3 * l^2
 template <int BINS> constexpr int64_t LIST_WORDS = 3LL * BINS * BINS;
-constexpr int NT_SOLVE = 512;  // solver workgroup (one-image and batched kernels alike)
+constexpr int NT_SOLVE = 1024;  // solver workgroup (one-image and batched kernels alike)
 constexpr int NT_BATCH = NT_SOLVE;
 // The batched kernel's register use allows one 512-thread workgroup per CU,
 // so its solver can take most of the CU's LDS as well.
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(NT) void k_lut(const uint32_t* hS, const float* tar
 template <int BITS>
 __global__ __launch_bounds__(NT_PIX) void k_remap(ImgDesc d, int64_t tile_px, const uint16_t* lut) {
   constexpr int BINS = Cfg<BITS>::BINS;
-  __shared__ uint2 tab[BINS];
+  __shared__ float2 tab[BINS];
   load_remap_table<BINS, NT_PIX>(lut, tab);
   __syncthreads();
   const int64_t P0 = (int64_t)blockIdx.x * tile_px;
@@ -101,7 +101,7 @@ union BatchSmem {
   HistSmem<BITS, NT_BATCH> hist;
   SolveSmem<Cfg<BITS>::BINS, NT_BATCH, BatchBudget<BITS>::value> solve;
   LutSmem<Cfg<BITS>::BINS, NT_BATCH> lut;
-  uint2 tab[Cfg<BITS>::BINS];
+  float2 tab[Cfg<BITS>::BINS];
 };
 
 __global__ void k_batch_reset(BatchHeader* hdr, ImageState* st, int bins) {
@@ -131,7 +131,7 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
     uint32_t v = 0;
 #pragma unroll
     for (int q = 0; q < ImageState::NSLOT; ++q)
-      v += __hip_atomic_load(s->slot(BINS, q) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      v += __hip_atomic_load(to_global(s->slot(BINS, q)) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (k < BINS) hs[k] = v;
     else if (k < 3 * BINS - 1) graw[k - BINS] = v;
   }
@@ -163,7 +163,7 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
   }
   drain_memory();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(&s->ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(to_global(&s->ready), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // image owning item `it` of a range [first[i], first[i] + count[i]) per image
@@ -219,17 +219,17 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
       } else {
         if (tab_img != i) {
           if (threadIdx.x == 0) {
-            while (__hip_atomic_load(&s->ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+            while (__hip_atomic_load(to_global(&s->ready), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
               __builtin_amdgcn_s_sleep(2);
             fence_acquire_agent();
           }
           __syncthreads();
           const uint16_t* lut = s->lut(BINS);
           for (int v = threadIdx.x; v < BINS; v += NT_BATCH) {
-            const uint32_t L = __hip_atomic_load(reinterpret_cast<const uint32_t*>(lut) + (v >> 1),
+            const uint32_t L = __hip_atomic_load(to_global(reinterpret_cast<const uint32_t*>(lut)) + (v >> 1),
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
-            sm.tab[v] = make_uint2(v ? recip_2v(v) : 0u, lv);
+            sm.tab[v] = remap_entry((uint32_t)v, lv);
           }
           __syncthreads();
           tab_img = i;
