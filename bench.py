@@ -28,6 +28,42 @@ from synthetic import config_seed, make_batch_shapes, make_image  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "Mpix/s end-to-end enhancement (batched vs plain, 1 GPU) + % HBM roofline"
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ("paper_2510_21100_amd/csrc/hr_kernels.hip", "paper_2510_21100_amd/csrc/hr_device.hpp",
+                  "paper_2510_21100_amd/csrc/hr_launch.hpp")
+
+
+def sources_digest() -> str:
+    """sha256 over the kernel sources: a traffic figure measured on other
+    sources no longer describes the kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name: str, bits: int):
+    """HBM bytes per launch of the batched kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
+    None when there is none for the current kernel sources."""
+    path = os.path.join(PROFILES, f"k_batch{bits}_{workload_name}.md")
+    try:
+        with open(path) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("bench-traffic:"):
+            for tok in line.split()[1:]:
+                k, _, v = tok.partition("=")
+                vals[k] = v
+    if vals.get("sources_sha256") != sources_digest() or "bytes_per_launch" not in vals:
+        return None
+    return int(vals["bytes_per_launch"])
 
 
 def _gen(args):
@@ -93,6 +129,43 @@ def cpu_baseline(imgs, bits, budget_s: float):
     }
 
 
+def time_plain(H, gimgs, outs, params, bins, stream, steps):
+    """The one-image form (three calls per image) on the same batch, and the
+    solver alone on the first image's histograms."""
+    import torch
+
+    pl_ws = H.Workspace(max_images=1, max_bins=bins)
+
+    def one_pass():
+        for g, o in zip(gimgs, outs):
+            hv, hg, _ = H.build_hist(g, pl_ws)
+            _, _, tg = H.solve(hv, hg, g.shape[0] * g.shape[1], params, pl_ws)
+            H.match(g, hv, tg, out=o, ws=pl_ws)
+
+    one_pass()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t1) * 1e3 / steps
+    npix = sum(g.shape[0] * g.shape[1] for g in gimgs)
+    plain_value = npix / (plain_ms * 1e-3) / 1e6
+
+    hv, hg, _ = H.build_hist(gimgs[0], pl_ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        H.solve(hv, hg, gimgs[0].shape[0] * gimgs[0].shape[1], params, pl_ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    solve_us = e0.elapsed_time(e1) * 1e3 / reps
+    pl_ws.close()
+    return plain_ms, plain_value, solve_us
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +179,11 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--remap-steps", type=int, default=0)
     ap.add_argument("--schedule", default=os.path.join(ROOT, "paper_2510_21100_amd", "schedule.json"))
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-image form and the solver timing")
+    ap.add_argument("--device-warmup-s", type=float, default=0.3,
+                    help="seconds of untimed batched calls before the warmup steps")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="after the batched steps, one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -147,6 +225,14 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ---- batched form --------------------------------------------------------
+    # device warm-up before the warmup steps: a first process on an idle GPU
+    # has been seen running several times slower for its first tens of ms
+    t_w = time.perf_counter()
+    n_w = 0
+    while time.perf_counter() - t_w < args.device_warmup_s or n_w < 2:
+        H.enhance_batch(gimgs, params, outs=outs, ws=ws)
+        torch.cuda.synchronize()
+        n_w += 1
     for _ in range(args.warmup):
         H.enhance_batch(gimgs, params, outs=outs, ws=ws)
     torch.cuda.synchronize()
@@ -166,37 +252,18 @@ def main():
     avg_launch_s = float(np.mean(launch_ms)) * 1e-3
     achieved = alg_bytes / avg_launch_s / 1e9
 
-    # ---- one-image form on the same batch -------------------------------------
-    pl_ws = H.Workspace(max_images=1, max_bins=bins)
-    pouts = outs
-    for _ in range(1):
-        for g, o in zip(gimgs, pouts):
-            hv, hg, _ = H.build_hist(g, pl_ws)
-            _, _, tg = H.solve(hv, hg, g.shape[0] * g.shape[1], params, pl_ws)
-            H.match(g, hv, tg, out=o, ws=pl_ws)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.plain_steps):
-        for g, o in zip(gimgs, pouts):
-            hv, hg, _ = H.build_hist(g, pl_ws)
-            _, _, tg = H.solve(hv, hg, g.shape[0] * g.shape[1], params, pl_ws)
-            H.match(g, hv, tg, out=o, ws=pl_ws)
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t1) * 1e3 / args.plain_steps
-    plain_value = npix / (plain_ms * 1e-3) / 1e6
+    if args.calibrate_copy_mb > 0:
+        nbytes = args.calibrate_copy_mb << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    # ---- solver alone (one image's histograms) ------------------------------
-    hv, hg, _ = H.build_hist(gimgs[0], pl_ws)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record(stream)
-    for _ in range(reps):
-        H.solve(hv, hg, gimgs[0].shape[0] * gimgs[0].shape[1], params, pl_ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    solve_us = e0.elapsed_time(e1) * 1e3 / reps
-
+    plain_ms = plain_value = solve_us = None
+    if not args.no_plain:
+        plain_ms, plain_value, solve_us = time_plain(H, gimgs, outs, params, bins, stream, args.plain_steps)
     cpu = None
     if args.cpu_budget > 0:
         cpu = cpu_baseline(imgs, bits, args.cpu_budget)
@@ -229,20 +296,22 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, bits),
             "kernel": f"k_batch<{bits}> (graph: descriptor copy + state reset + persistent kernel)",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
         },
-        "plain": {"value": round(plain_value, 1), "unit": "Mpix/s", "ms_per_step": round(plain_ms, 3),
-                  "batched_over_plain": round(value / plain_value, 3)},
-        "solve_us_per_image": round(solve_us, 1),
+        "plain": None if plain_ms is None else {
+            "value": round(plain_value, 1), "unit": "Mpix/s", "ms_per_step": round(plain_ms, 3),
+            "batched_over_plain": round(value / plain_value, 3),
+            "form": "one image per call: hr_build_hist, hr_solve, hr_match launched per image"},
+        "solve_us_per_image": None if solve_us is None else round(solve_us, 1),
         "gen_seconds": round(gen_s, 1),
+        "device_warmup_calls": n_w,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     ws.close()
-    pl_ws.close()
 
 
 if __name__ == "__main__":
