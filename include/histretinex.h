@@ -167,6 +167,54 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
                            float* illum, float* refl, float* target, hr_workspace* ws,
                            void* stream);
 
+/* ---- the differentiated form (256 levels; not part of the paper) ------------------
+ *
+ * Gradients of an enhancement loss with respect to the prior weights alpha,
+ * beta of Eq. (10) and the target histogram h~ of Eq. (20).  The exact LUT is
+ * piecewise constant in h~, so the loss uses a soft matching map m(v): the
+ * piecewise-linear inverse of the normalised target CDF F~ through the knots
+ * (k + 1/2, F~(k)) (and (-1/2, 0)), evaluated at the mid-rank image CDF u(v)
+ * that the exact LUT uses, clamped to [0, l-1]; round(m(v)) = LUT[v].  The
+ * loss of an image is the mean over its pixels and channels of
+ * (c m(V) / (V (l-1)) - t_c)^2 (m(0) / (l-1) for black pixels) against a
+ * target image t.  H_C(S), H_C(grad S) and the classes are constants.
+ * Every call handles n images of one batch; arrays indexed [n] are per image.
+ */
+
+/* Alg. 1 for p->iters passes on each of n histogram pairs, keeping the
+ * dense (L, R) of t = 0, ckpt_every, ..., iters (probability units).
+ *  hist_v, hist_grad : device uint32[n][256] (from hr_build_hist)
+ *  ckpt_every        : 1..16, and p->iters must be a multiple of it
+ *  ckpt              : device float[n][iters/ckpt_every + 1][2][256], out:
+ *                      L at [..][0][level], R at [..][1][level]
+ *  target            : device float[n][256], out: h~ of Eq. (20), counts */
+hr_status hr_solve_ckpt(const uint32_t* hist_v, const uint32_t* hist_grad, int32_t n, const hr_params* p,
+                        int32_t ckpt_every, float* ckpt, float* target, hr_workspace* ws, void* stream);
+
+/* Soft-matching loss of n 8-bit images and its gradient with respect to h~.
+ *  in         : host array [n] of image descriptors (8-bit)
+ *  target_img : host array [n] of device pointers to float[H][W][3] (tight
+ *               rows, 4-byte aligned): the target t of each image
+ *  hist_v     : device uint32[n][256], H_C(S) of each image
+ *  target     : device float[n][256], h~ (non-negative, positive sum)
+ *  loss       : device double[n], out: the loss of each image
+ *  dtarget    : device float[n][256], out: dLoss_i/dh~_i
+ * Uses the workspace's scratch; calls on one workspace are stream-ordered. */
+hr_status hr_softmatch_loss_grad(const hr_image* in, const float* const* target_img, int32_t n,
+                                 const uint32_t* hist_v, const float* target, double* loss, float* dtarget,
+                                 hr_workspace* ws, void* stream);
+
+/* Reverse pass of hr_solve_ckpt: given dLoss/dh~ of each image, the
+ * gradient with respect to alpha and beta through Eq. (20) and the K
+ * passes of Eqs. (11)-(15), recomputing each checkpoint segment.
+ *  hist_v, hist_grad, p, ckpt_every : as passed to hr_solve_ckpt
+ *  ckpt     : device float, as written by hr_solve_ckpt
+ *  dtarget  : device float[n][256], dLoss/dh~
+ *  dalpha, dbeta : device double[n], out: per-image gradients */
+hr_status hr_solve_vjp(const uint32_t* hist_v, const uint32_t* hist_grad, int32_t n, const hr_params* p,
+                       int32_t ckpt_every, const float* ckpt, const float* dtarget, double* dalpha, double* dbeta,
+                       hr_workspace* ws, void* stream);
+
 /* ---- support ------------------------------------------------------------------ */
 
 const char* hr_status_string(hr_status s);

@@ -25,6 +25,7 @@ HR_FLAG_HIST_MASS = 0x2
 EXPORTS = (
     "hr_workspace_create", "hr_workspace_destroy", "hr_workspace_set_schedule", "hr_get_flags",
     "hr_build_hist", "hr_solve", "hr_match", "hr_enhance_batch",
+    "hr_solve_ckpt", "hr_softmatch_loss_grad", "hr_solve_vjp",
     "hr_status_string", "hr_last_error", "hr_abi_version",
 )
 
@@ -65,6 +66,9 @@ def _load():
         "hr_match": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, P, C.c_int64, P, P, P]),
         "hr_enhance_batch": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.POINTER(C.c_int64), C.c_int32,
                                        C.c_int32, C.POINTER(HrParams), P, P, P, P, P, P]),
+        "hr_solve_ckpt": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P]),
+        "hr_softmatch_loss_grad": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.c_int32, P, P, P, P, P, P]),
+        "hr_solve_vjp": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P, P, P]),
         "hr_status_string": (C.c_char_p, [C.c_int]),
         "hr_last_error": (C.c_char_p, []),
         "hr_abi_version": (C.c_int32, []),

@@ -49,6 +49,14 @@ int64_t plain_tile_px(int bits, int64_t npix, int cu_count, int64_t min_steps) {
   return steps * step;
 }
 
+// differentiated form scratch: the soft map (256 floats) and the pixel-pass
+// sums (257 u64) per image
+constexpr int kDiffBins = 256;
+size_t diff_map_bytes(int n) { return sizeof(float) * kDiffBins * (size_t)n; }
+size_t diff_bytes(int max_images) {
+  return diff_map_bytes(max_images) + sizeof(unsigned long long) * (kDiffBins + 1) * (size_t)max_images;
+}
+
 size_t table_bytes(int max_images) {
   return sizeof(hr::BatchHeader) + (size_t)max_images * sizeof(hr::ImgDesc);
 }
@@ -75,6 +83,7 @@ struct hr_workspace {
   int64_t lists_words = 0;       // words per image slot
   uint8_t* d_table = nullptr;    // BatchHeader + ImgDesc[max_images]
   uint32_t* d_state = nullptr;   // ImageState per image
+  uint8_t* d_diff = nullptr;     // differentiated form: soft map [max_images][256] float, sums [max_images][257] u64
   uint8_t* h_stage[kStaging] = {nullptr, nullptr};
   hipEvent_t ev[kStaging] = {nullptr, nullptr};
   bool ev_used[kStaging] = {false, false};
@@ -177,6 +186,7 @@ void release(hr_workspace* ws) {
   (void)hipFree(ws->d_lists);
   (void)hipFree(ws->d_table);
   (void)hipFree(ws->d_state);
+  (void)hipFree(ws->d_diff);
   delete ws;
 }
 
@@ -225,6 +235,7 @@ hr_status hr_workspace_create(int32_t max_images, int32_t max_bins, hr_workspace
   HR_HIP_WS(hipMalloc(&ws->d_lists, sizeof(uint32_t) * ws->lists_words * max_images));
   HR_HIP_WS(hipMalloc(&ws->d_table, table_bytes(max_images)));
   HR_HIP_WS(hipMalloc(&ws->d_state, sizeof(uint32_t) * hr::ImageState::words(max_bins) * max_images));
+  HR_HIP_WS(hipMalloc(&ws->d_diff, diff_bytes(max_images)));
   for (int s = 0; s < kStaging; ++s) {
     HR_HIP_WS(hipHostMalloc(&ws->h_stage[s], table_bytes(max_images), hipHostMallocDefault));
     std::memset(ws->h_stage[s], 0, table_bytes(max_images));
@@ -399,6 +410,87 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   HR_HIP(hipEventRecord(ws->ev[slot], s));
   ws->ev_used[slot] = true;
   ws->slot = (slot + 1) % kStaging;
+  return HR_OK;
+}
+
+
+// ---- differentiated form -------------------------------------------------------
+
+static hr_status check_diff(const hr_params* p, int32_t n, int32_t ckpt_every, const char* what) {
+  hr_status st = check_params(p, 8);
+  if (st) return st;
+  if (n < 1) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": n must be >= 1");
+  if (ckpt_every < 1 || ckpt_every > hr::launch::diff_seg_max())
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": ckpt_every must be in 1.." +
+                                        std::to_string(hr::launch::diff_seg_max()));
+  if (p->iters % ckpt_every != 0)
+    return fail(HR_ERR_INVALID_ARG, std::string(what) + ": iters must be a multiple of ckpt_every");
+  return HR_OK;
+}
+
+hr_status hr_solve_ckpt(const uint32_t* hist_v, const uint32_t* hist_grad, int32_t n, const hr_params* p,
+                        int32_t ckpt_every, float* ckpt, float* target, hr_workspace* ws, void* stream) {
+  hr_status st = check_diff(p, n, ckpt_every, "hr_solve_ckpt");
+  if (st) return st;
+  if (!hist_v || !hist_grad || !ckpt || !target) return fail(HR_ERR_INVALID_ARG, "hr_solve_ckpt: NULL pointer");
+  if ((st = check_ws(ws, 256))) return st;
+  if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_solve_ckpt: n exceeds the workspace's max_images");
+  hr::SolveParams sp = solve_params(p);
+  sp.ckpt_every = ckpt_every;
+  HR_HIP(hr::launch::solve_ckpt(n, hist_v, hist_grad, sp, p->iters / ckpt_every + 1, ckpt, target, ws->d_lists,
+                                ws->d_flags, static_cast<hipStream_t>(stream)));
+  return HR_OK;
+}
+
+hr_status hr_softmatch_loss_grad(const hr_image* in, const float* const* target_img, int32_t n,
+                                 const uint32_t* hist_v, const float* target, double* loss, float* dtarget,
+                                 hr_workspace* ws, void* stream) {
+  if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_softmatch_loss_grad: n must be >= 1");
+  if (!in || !target_img || !hist_v || !target || !loss || !dtarget)
+    return fail(HR_ERR_INVALID_ARG, "hr_softmatch_loss_grad: NULL pointer");
+  std::vector<hr::ImgDesc> descs((size_t)n);
+  int64_t max_npix = 0;
+  hr_status st;
+  for (int i = 0; i < n; ++i) {
+    if ((st = make_desc(&in[i], 8, "hr_softmatch_loss_grad", &descs[i]))) return st;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(target_img[i]);
+    if (!a || (a & 3u)) return fail(HR_ERR_INVALID_ARG, "hr_softmatch_loss_grad: target image NULL or misaligned");
+    descs[i].out = reinterpret_cast<uint8_t*>(const_cast<float*>(target_img[i]));
+    descs[i].out_stride = 12LL * descs[i].W;
+    descs[i].slot = i;
+    max_npix = std::max(max_npix, descs[i].npix);
+  }
+  if ((st = check_ws(ws, 256))) return st;
+  if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_softmatch_loss_grad: n exceeds the workspace's max_images");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int slot = ws->slot;
+  if (ws->ev_used[slot]) HR_HIP(hipEventSynchronize(ws->ev[slot]));
+  uint8_t* stage = ws->h_stage[slot];
+  std::memcpy(stage, descs.data(), sizeof(hr::ImgDesc) * (size_t)n);
+  auto* desc_d = reinterpret_cast<hr::ImgDesc*>(ws->d_table + sizeof(hr::BatchHeader));
+  HR_HIP(hipMemcpyAsync(desc_d, stage, sizeof(hr::ImgDesc) * (size_t)n, hipMemcpyHostToDevice, s));
+  auto* m_tab = reinterpret_cast<float*>(ws->d_diff);
+  auto* acc = reinterpret_cast<unsigned long long*>(ws->d_diff + diff_map_bytes(ws->max_images));
+  HR_HIP(hr::launch::softmatch(n, desc_d, max_npix, hist_v, target, m_tab, acc, loss, dtarget, s));
+  HR_HIP(hipEventRecord(ws->ev[slot], s));
+  ws->ev_used[slot] = true;
+  ws->slot = (slot + 1) % kStaging;
+  return HR_OK;
+}
+
+hr_status hr_solve_vjp(const uint32_t* hist_v, const uint32_t* hist_grad, int32_t n, const hr_params* p,
+                       int32_t ckpt_every, const float* ckpt, const float* dtarget, double* dalpha, double* dbeta,
+                       hr_workspace* ws, void* stream) {
+  hr_status st = check_diff(p, n, ckpt_every, "hr_solve_vjp");
+  if (st) return st;
+  if (!hist_v || !hist_grad || !ckpt || !dtarget || !dalpha || !dbeta)
+    return fail(HR_ERR_INVALID_ARG, "hr_solve_vjp: NULL pointer");
+  if ((st = check_ws(ws, 256))) return st;
+  if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_solve_vjp: n exceeds the workspace's max_images");
+  hr::SolveParams sp = solve_params(p);
+  sp.ckpt_every = ckpt_every;
+  HR_HIP(hr::launch::solve_vjp(n, hist_v, hist_grad, sp, p->iters / ckpt_every + 1, ckpt, dtarget, dalpha, dbeta,
+                               ws->d_flags, static_cast<hipStream_t>(stream)));
   return HR_OK;
 }
 

@@ -1096,12 +1096,22 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   __syncthreads();
 }
 
+// Dense copy of the current (L, R) into state[0..2 BINS): level k of L at
+// [k], of R at [BINS + k], 0 at unoccupied levels.
+template <int BINS, int NT>
+__device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state) {
+  for (int k = threadIdx.x; k < BINS; k += NT) {
+    state[k] = sm.sd[k] > 0.f ? sm.lc[sm.PA[k]] : 0.f;
+    state[BINS + k] = sm.PB[k + 1] > sm.PB[k] ? sm.rc[sm.PB[k]] : 0.f;
+  }
+}
+
 // The Alg. 1 loop.  LIST: class totals from the class list (else per-class
 // gathers over row runs); CELLS_LDS / TAB: where the list and the class
 // tables live, so that every access compiles to its address space.
 template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
 __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
-                        const SolveParams& p) {
+                        const SolveParams& p, float* ckpt) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
   constexpr uint32_t MASK = (1u << SH) - 1;
@@ -1129,6 +1139,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   __syncthreads();
 
   for (int it = 0; it < p.iters; ++it) {
+    if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0) write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS);
     // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m
     {
       if constexpr (LIST) {
@@ -1274,17 +1285,25 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     }
     __syncthreads();
   }
+  if (ckpt && p.ckpt_every > 0 && p.iters % p.ckpt_every == 0)
+    write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS);
 }
 
-// Alg. 1 (Eqs. 11-15) for p.iters passes and the target histogram of
-// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); gcells:
-// global scratch (gcap cells) for the class list when it does not fit in
-// LDS.  Writes
-// illum/refl/target (counts, dense over the l levels) when non-null.
-template <int BINS, int NT, int BUDGET>
-__device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
-                            SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
-                            float* illum, float* refl, float* target, uint32_t* flags) {
+// LDS budget of the one-image solver: most of a CU's 160 KB.
+constexpr int SOLVE_BUDGET_PLAIN = 150 * 1024;
+// solver scratch per image in global memory (32-bit words), as allocated by
+// the workspace: 3 * l^2
+template <int BINS> constexpr int64_t LIST_WORDS = 3LL * BINS * BINS;
+constexpr int NT_SOLVE = 1024;  // solver workgroup (one-image and batched kernels alike)
+
+// Setup of the solve (Alg. 1 initialisation): masses, the occupied levels A
+// of s and B of g (compacted, with their prefix counts PA, PB), s and g in
+// probability units, L = s and R = g.  Returns N = sum of hS.  npix < 0 skips
+// the check of the mass against npix (the gradient histogram is still
+// checked against hS).
+template <int BINS, int NT>
+__device__ uint64_t solve_setup(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveCore<BINS, NT>& sm,
+                                uint32_t* flags) {
   const int t = threadIdx.x;
   uint64_t ms = 0, mg = 0;
   for (int k = t; k < BINS; k += NT) {
@@ -1293,7 +1312,7 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
   }
   const uint64_t Ns = block_sum<NT>(ms, sm.redu);
   const uint64_t Ng = block_sum<NT>(mg, sm.redu);
-  if (t == 0 && (Ns != (uint64_t)npix || Ng != Ns)) atomicOr(flags, FLAG_HIST_MASS);
+  if (t == 0 && ((npix >= 0 && Ns != (uint64_t)npix) || Ng != Ns)) atomicOr(flags, FLAG_HIST_MASS);
   for (int k = t; k < BINS + 1; k += NT) sm.PA[k] = (k < BINS && hS[k]) ? 1 : 0;
   __syncthreads();
   const int nA = block_scan<NT, int32_t>(sm.PA, BINS + 1, sm.redi);
@@ -1328,16 +1347,32 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
   }
   for (int j = t; j < nB; j += NT) sm.rc[j] = sm.gc[j];  // R(0) = H_C(grad S)
   __syncthreads();
+  return Ns;
+}
+
+// Alg. 1 (Eqs. 11-15) for p.iters passes and the target histogram of
+// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); gcells:
+// global scratch (gcap cells) for the class list when it does not fit in
+// LDS.  Writes illum/refl/target (counts, dense over the l levels) when
+// non-null, and with ckpt non-null and p.ckpt_every > 0 the dense (L, R) of
+// t = 0, every, 2 every, ... (2 l floats each, see write_state).
+template <int BINS, int NT, int BUDGET>
+__device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
+                            SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
+                            float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr) {
+  const int t = threadIdx.x;
+  const uint64_t Ns = solve_setup<BINS, NT>(hS, hG, npix, sm, flags);
+  const int nA = sm.nA, nB = sm.nB;
   if constexpr (BINS == 256) {
     build_class_list<BINS, NT, BUDGET>(sm, gcells, gcap);
     if (!sm.use_list)
-      iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p);
+      iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
     else if (!sm.cells_lds)
-      iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p);
+      iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p, ckpt);
     else if (sm.tab_lds)
-      iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p);
+      iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p, ckpt);
     else
-      iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p);
+      iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p, ckpt);
   } else {
     if (t == 0) {
       sm.C = 0;
@@ -1347,7 +1382,7 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
       sm.nBp = (nB + 3) & ~3;
     }
     __syncthreads();
-    iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p);
+    iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
   }
 
   // Eqs. (17)-(20): target_k = N * sum over cells with round(theta_a * b) = k

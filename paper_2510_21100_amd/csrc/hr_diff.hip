@@ -1,0 +1,489 @@
+// Differentiated form of the HistRetinex solve and matching (8-bit, 256
+// levels).  Not part of the paper: the exact LUT is piecewise constant in the
+// target histogram, so the gradient runs through a soft matching map m(v),
+// the piecewise-linear inverse of the normalised target CDF through the knots
+// (k + 1/2, F~(k)), evaluated at the mid-rank source CDF u(v); round(m(v)) is
+// the exact LUT value.  The loss of an image is the mean over pixels and
+// channels of (c m(V) / (V (l-1)) - t_c)^2 against a target image t.
+//
+//   k_solve_ckpt  Alg. 1 forward with the dense (L, R) every few passes
+//   k_softmap     m(v) from H_C(S) and the target h~
+//   k_softloss    one pixel pass: loss and G[v] = sum over pixels at level v
+//                 of sum_c (out_c - t_c) * (c, or 1 for black pixels)
+//   k_softgrad    dLoss/dm(v), then dLoss/dh~ through the inverse-CDF map
+//   k_solve_vjp   dLoss/dh~ -> Eq. (20) adjoint -> reverse through the
+//                 passes of Eqs. (11)-(15), recomputing each checkpoint
+//                 segment -> dLoss/dalpha, dLoss/dbeta
+//
+// Fixed-point (2^-24 and 2^-32) integer atomics keep the pixel-pass sums
+// independent of the order in which workgroups arrive.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "hr_device.hpp"
+#include "hr_launch.hpp"
+
+namespace hr {
+
+constexpr int DIFF_BINS = 256;
+constexpr int NT_VJP = 256;   // one thread per level in the reverse pass
+constexpr int SEG_MAX = 16;   // largest checkpoint interval
+constexpr double G_SCALE = 16777216.0;       // 2^24: fixed point of G[v]
+constexpr double LOSS_SCALE = 4294967296.0;  // 2^32: fixed point of the squared errors
+
+// ---------------------------------------------------------------------------
+// forward with checkpoints: one workgroup per image
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(NT_SOLVE) void k_solve_ckpt(const uint32_t* hv, const uint32_t* hg, SolveParams p,
+                                                          int ncp, float* ckpt, float* target, uint32_t* lists,
+                                                          uint32_t* flags) {
+  constexpr int BINS = DIFF_BINS;
+  __shared__ SolveSmem<BINS, NT_SOLVE, SOLVE_BUDGET_PLAIN> sm;
+  const int i = blockIdx.x;
+  using cell_t = typename CellT<BINS>::type;
+  solve_image<BINS, NT_SOLVE, SOLVE_BUDGET_PLAIN>(
+      hv + (size_t)i * BINS, hg + (size_t)i * BINS, -1, p, sm,
+      reinterpret_cast<cell_t*>(lists + (size_t)i * LIST_WORDS<BINS>),
+      LIST_WORDS<BINS> * 4 / (int64_t)sizeof(cell_t), nullptr, nullptr, target + (size_t)i * BINS, flags,
+      ckpt + (size_t)i * ncp * 2 * BINS);
+}
+
+// ---------------------------------------------------------------------------
+// soft matching map
+// ---------------------------------------------------------------------------
+
+struct SoftSmem {
+  double F[DIFF_BINS];    // normalised target CDF
+  double u[DIFF_BINS];    // mid-rank source CDF
+  uint64_t cs[DIFF_BINS];
+  double redd[DIFF_BINS / 64];
+  uint64_t redu[DIFF_BINS / 64];
+  double gF[DIFF_BINS];
+  double dm[DIFF_BINS];
+};
+
+// CDFs of one image: F~(k) = C(k) / C(l-1) with C the running sum of the
+// target, u(v) = (cS(v-1) + cS(v)) / (2N).  NT = DIFF_BINS threads.
+__device__ double soft_cdfs(const uint32_t* hS, const float* target, SoftSmem& sm, uint64_t& N) {
+  constexpr int BINS = DIFF_BINS;
+  const int t = threadIdx.x;
+  sm.F[t] = (double)target[t];
+  sm.cs[t] = hS[t];
+  __syncthreads();
+  const double S = block_scan<BINS, double, true>(sm.F, BINS, sm.redd);
+  N = block_scan<BINS, uint64_t, true>(sm.cs, BINS, sm.redu);
+  sm.F[t] = t == BINS - 1 ? 1.0 : sm.F[t] / S;
+  sm.u[t] = (double)(2 * sm.cs[t] - hS[t]) / (2.0 * (double)N);
+  __syncthreads();
+  return S;
+}
+
+// k = min{k : F~(k) >= u}; lo = F~(k-1) (0 for k = 0), hi = F~(k)
+__device__ inline int soft_branch(const SoftSmem& sm, double u, double& lo, double& hi) {
+  int a = 0, b = DIFF_BINS - 1;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (sm.F[mid] >= u) b = mid; else a = mid + 1;
+  }
+  lo = a > 0 ? sm.F[a - 1] : 0.0;
+  hi = sm.F[a];
+  return a;
+}
+
+__global__ __launch_bounds__(DIFF_BINS) void k_softmap(const uint32_t* hv, const float* target, float* m_out) {
+  constexpr int BINS = DIFF_BINS;
+  __shared__ SoftSmem sm;
+  const int i = blockIdx.x, t = threadIdx.x;
+  uint64_t N;
+  soft_cdfs(hv + (size_t)i * BINS, target + (size_t)i * BINS, sm, N);
+  double lo, hi;
+  const int k = soft_branch(sm, sm.u[t], lo, hi);
+  const double m = (double)k - 0.5 + (sm.u[t] - lo) / (hi - lo);
+  m_out[(size_t)i * BINS + t] = (float)fmin(fmax(m, 0.0), (double)(BINS - 1));
+}
+
+// ---------------------------------------------------------------------------
+// pixel pass: loss and the weighted level histogram G
+// ---------------------------------------------------------------------------
+
+// One workgroup per (tile, image); desc[i].in is the image, desc[i].out the
+// FP32 HWC target image (tight rows), acc[i] holds BINS int64 sums of G in
+// 2^-24 units followed by the squared-error sum in 2^-32 units.
+__global__ __launch_bounds__(NT_PIX) void k_softloss(const ImgDesc* desc, const float* m_tab, int64_t tile_px,
+                                                     unsigned long long* acc) {
+  constexpr int BINS = DIFF_BINS;
+  constexpr int PX = 16;
+  __shared__ float scale[BINS];
+  __shared__ unsigned long long g_lds[BINS];
+  __shared__ float red[NT_PIX / 64];
+  const int i = blockIdx.y, t = threadIdx.x;
+  const ImgDesc d = desc[i];
+  const int64_t P0 = (int64_t)blockIdx.x * tile_px;
+  if (P0 >= d.npix) return;  // uniform: this image has fewer tiles
+  const int64_t P1 = min(P0 + tile_px, d.npix);
+  const float* mt = m_tab + (size_t)i * BINS;
+  for (int v = t; v < BINS; v += NT_PIX) {
+    scale[v] = v ? mt[v] / (float)(v * (BINS - 1)) : 0.f;
+    g_lds[v] = 0ull;
+  }
+  __syncthreads();
+  const float black = mt[0] / (float)(BINS - 1);
+  const gptr<const float> tg = to_global(reinterpret_cast<const float*>(d.out));
+  float sq = 0.f;
+  for (int64_t p = P0 + (int64_t)t * PX; p < P1; p += (int64_t)NT_PIX * PX) {
+    const int n = (int)min((int64_t)PX, P1 - p);
+    for (int k = 0; k < n; ++k) {
+      const int64_t q = p + k;
+      const int64_t y = q / d.W;
+      const int x = (int)(q - y * d.W);
+      const gptr<const uint8_t> px = to_global(d.in + y * d.in_stride) + 3 * x;
+      const uint32_t c0 = px[0], c1 = px[1], c2 = px[2];
+      const uint32_t V = umax3(c0, c1, c2);
+      const float s = scale[V];
+      const gptr<const float> tp = tg + 3 * q;
+      float gsum = 0.f;
+      const uint32_t cc[3] = {c0, c1, c2};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float o = V ? (float)cc[c] * s : black;
+        const float e = o - tp[c];
+        sq = fmaf(e, e, sq);
+        gsum = fmaf(e, V ? (float)cc[c] : 1.f, gsum);
+      }
+      const long long gq = __double2ll_rn((double)gsum * G_SCALE);
+      atomicAdd(&g_lds[V], (unsigned long long)gq);
+    }
+  }
+  const float tot = block_sum<NT_PIX>(sq, red);
+  __syncthreads();
+  unsigned long long* out = acc + (size_t)i * (BINS + 1);
+  for (int v = t; v < BINS; v += NT_PIX)
+    if (g_lds[v]) atomicAdd(out + v, g_lds[v]);
+  if (t == 0) atomicAdd(out + BINS, (unsigned long long)__double2ll_rn((double)tot * LOSS_SCALE));
+}
+
+// ---------------------------------------------------------------------------
+// dLoss/dm(v) -> dLoss/dh~ (one workgroup per image)
+// ---------------------------------------------------------------------------
+
+// m(v) = k - 1/2 + (u - lo) / (hi - lo) with lo = F~(k-1), hi = F~(k):
+//   dm/dlo = (u - hi) / (hi - lo)^2,  dm/dhi = -(u - lo) / (hi - lo)^2;
+// F~(j) = C(j) / C(l-1):  dF~(j)/dh~_i = ([i <= j] - F~(j)) / C(l-1).
+__global__ __launch_bounds__(DIFF_BINS) void k_softgrad(const uint32_t* hv, const float* target,
+                                                        const unsigned long long* acc, double* loss,
+                                                        float* dtarget) {
+  constexpr int BINS = DIFF_BINS;
+  __shared__ SoftSmem sm;
+  const int i = blockIdx.x, t = threadIdx.x;
+  const uint32_t* hS = hv + (size_t)i * BINS;
+  uint64_t N;
+  const double S = soft_cdfs(hS, target + (size_t)i * BINS, sm, N);
+  const unsigned long long* a = acc + (size_t)i * (BINS + 1);
+  const double inv3N = 1.0 / (3.0 * (double)N);
+  {
+    const double G = (double)(long long)a[t] / G_SCALE;
+    double lo, hi;
+    const int k = soft_branch(sm, sm.u[t], lo, hi);
+    const double m = (double)k - 0.5 + (sm.u[t] - lo) / (hi - lo);
+    const bool clamped = m < 0.0 || m > (double)(BINS - 1);
+    const double dLdm = clamped ? 0.0 : 2.0 * G * inv3N / (double)(t ? t * (BINS - 1) : (BINS - 1));
+    sm.dm[t] = hS[t] ? dLdm : 0.0;
+    sm.gF[t] = 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    // fixed order over the levels: deterministic
+    for (int v = 0; v < BINS; ++v) {
+      if (sm.dm[v] == 0.0) continue;
+      double lo, hi;
+      const int k = soft_branch(sm, sm.u[v], lo, hi);
+      const double w = hi - lo;
+      if (k > 0) sm.gF[k - 1] += sm.dm[v] * (sm.u[v] - hi) / (w * w);
+      sm.gF[k] += sm.dm[v] * -(sm.u[v] - lo) / (w * w);
+    }
+    double dot = 0.0;
+    for (int k = 0; k < BINS; ++k) dot += sm.gF[k] * sm.F[k];
+    double suffix = 0.0;
+    for (int k = BINS - 1; k >= 0; --k) {
+      suffix += sm.gF[k];
+      sm.dm[k] = (suffix - dot) / S;
+    }
+    loss[i] = (double)(long long)a[BINS] / LOSS_SCALE * inv3N;
+  }
+  __syncthreads();
+  dtarget[(size_t)i * BINS + t] = (float)sm.dm[t];
+}
+
+// ---------------------------------------------------------------------------
+// reverse pass of the solve (one workgroup per image, one thread per level)
+// ---------------------------------------------------------------------------
+
+struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
+  float segl[SEG_MAX][DIFF_BINS], segr[SEG_MAX][DIFF_BINS];  // states of the current segment (compacted)
+  float lt[DIFF_BINS], rt[DIFF_BINS];                        // state of the pass being reversed
+  float dcl[DIFF_BINS], rh[DIFF_BINS];                       // class totals and rho by class
+  float u[DIFF_BINS], rp[DIFF_BINS], v[DIFF_BINS], lp[DIFF_BINS];            // u_b, R', v_a, L'
+  float l2[DIFF_BINS], w[DIFF_BINS];                         // L^2, R' R
+  float lb[DIFF_BINS], rb[DIFF_BINS];                        // adjoints of the state
+  float lbp[DIFF_BINS], rbp[DIFF_BINS];                      // adjoints of L', R'
+  float vb[DIFF_BINS], ub[DIFF_BINS];                        // adjoints of v, u
+  float ta[DIFF_BINS], tb[DIFF_BINS];                        // gather results
+  float rhb[DIFF_BINS];                              // adjoint of rho, then of d
+  float gH[DIFF_BINS];                               // dLoss/dh~ (dense)
+  double theta[DIFF_BINS];                           // Eq. (17) on A
+  float redv[NT_VJP / 64];
+  double redd[NT_VJP / 64];
+  float sc_Q, sc_P, sc_Sl, sc_Sr;
+};
+
+// out[j] = sum_i x[i] * tab[class(A_i, B_j)] for j < nB (one thread per j)
+template <typename ClassFn>
+__device__ inline void col_gather(const VjpSmem& sm, const float* x, const float* tab, float* out, ClassFn cls) {
+  const int j = threadIdx.x;
+  if (j < sm.nB) {
+    float a4[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < sm.nA; ++i) a4[i & 3] = fmaf(x[i], tab[cls(i, j)], a4[i & 3]);
+    out[j] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  }
+}
+
+// out[i] = sum_j y[j] * tab[class(A_i, B_j)] for i < nA (one thread per i)
+template <typename ClassFn>
+__device__ inline void row_gather(const VjpSmem& sm, const float* y, const float* tab, float* out, ClassFn cls) {
+  const int i = threadIdx.x;
+  if (i < sm.nA) {
+    float a4[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < sm.nB; ++j) a4[j & 3] = fmaf(y[j], tab[cls(i, j)], a4[j & 3]);
+    out[i] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  }
+}
+
+// out[m] = sum over the cells (i, j) of class m of p1[i] q1[j] + p2[i] q2[j]
+// (the second term only with TWO); classes with s_m = 0 get 0.
+template <bool TWO>
+__device__ inline void class_sums(const VjpSmem& sm, const float* p1, const float* q1, const float* p2,
+                                  const float* q2, float* out) {
+  const int m = threadIdx.x;
+  float acc = 0.f;
+  if (sm.sd[m] > 0.f) {
+    for (int i = sm.PA[m]; i < sm.nA; ++i) {
+      int jlo, jhi;
+      class_run<DIFF_BINS>(sm, i, m, jlo, jhi);
+      float a1 = 0.f, a2 = 0.f;
+      for (int j = jlo; j < jhi; ++j) {
+        a1 += q1[j];
+        if (TWO) a2 += q2[j];
+      }
+      acc = fmaf(p1[i], a1, acc);
+      if (TWO) acc = fmaf(p2[i], a2, acc);
+    }
+  }
+  out[m] = acc;
+}
+
+struct IdxClass {
+  const VjpSmem& sm;
+  __device__ int operator()(int i, int j) const { return class_of<DIFF_BINS>(sm.A[i], sm.B[j]); }
+};
+struct Idx1Class {
+  const VjpSmem& sm;
+  __device__ int operator()(int i, int j) const {
+    return (int)floor(sm.theta[i] * (double)sm.B[j] + 0.5);  // Eq. (19), as in the forward
+  }
+};
+
+// The quantities of one pass from the state (lt, rt): d, rho (Eq. 11),
+// u and R' (Eq. 13), v and L' (Eq. 12), and the sums Q, P, Sl, Sr.
+__device__ void vjp_forward_pass(VjpSmem& sm, const SolveParams& p) {
+  const int t = threadIdx.x;
+  const int nA = sm.nA, nB = sm.nB;
+  class_sums<false>(sm, sm.lt, sm.rt, nullptr, nullptr, sm.dcl);
+  const float l2 = t < nA ? sm.lt[t] * sm.lt[t] : 0.f;
+  if (t < nA) sm.l2[t] = l2;
+  __syncthreads();
+  sm.rh[t] = sm.dcl[t] > 0.f ? sm.sd[t] / sm.dcl[t] : 0.f;
+  const float Q = block_sum<NT_VJP>(l2, sm.redv);  // synchronises
+  col_gather(sm, sm.l2, sm.rh, sm.u, IdxClass{sm});
+  __syncthreads();
+  float rpv = 0.f;
+  if (t < nB) {
+    rpv = (sm.rt[t] * sm.u[t] + p.beta * sm.gc[t]) / (Q + p.beta);
+    sm.rp[t] = rpv;
+    sm.w[t] = rpv * sm.rt[t];
+  }
+  const float Sr = block_sum<NT_VJP>(rpv, sm.redv);
+  const float P = block_sum<NT_VJP>(rpv * rpv, sm.redv);
+  row_gather(sm, sm.w, sm.rh, sm.v, IdxClass{sm});
+  __syncthreads();
+  float lpv = 0.f;
+  if (t < nA) {
+    lpv = (sm.lt[t] * sm.v[t] + p.alpha * sm.sc[t]) / (P + p.alpha);
+    sm.lp[t] = lpv;
+  }
+  const float Sl = block_sum<NT_VJP>(lpv, sm.redv);
+  if (t == 0) {
+    sm.sc_Q = Q;
+    sm.sc_P = P;
+    sm.sc_Sl = Sl;
+    sm.sc_Sr = Sr;
+  }
+  __syncthreads();
+}
+
+// Reverse of one pass: (lb, rb) = adjoints of the normalised outputs on
+// entry, of the pass's input state (lt, rt) on exit.  Adds the pass's
+// contributions to dalpha, dbeta (every thread holds the same totals).
+__device__ void vjp_backward_pass(VjpSmem& sm, const SolveParams& p, double& dalpha, double& dbeta) {
+  const int t = threadIdx.x;
+  const int nA = sm.nA, nB = sm.nB;
+  const float Q = sm.sc_Q, P = sm.sc_P, Sl = sm.sc_Sl, Sr = sm.sc_Sr;
+  const float Dl = P + p.alpha, Dr = Q + p.beta;
+  // Eqs. (14), (15): L+ = L'/Sl, R+ = R'/Sr
+  const float dotl = block_sum<NT_VJP>(t < nA ? sm.lb[t] * sm.lp[t] / Sl : 0.f, sm.redv);
+  const float dotr = block_sum<NT_VJP>(t < nB ? sm.rb[t] * sm.rp[t] / Sr : 0.f, sm.redv);
+  float lbp = 0.f, rbp = 0.f;
+  if (t < nA) lbp = (sm.lb[t] - dotl) / Sl;
+  if (t < nB) rbp = (sm.rb[t] - dotr) / Sr;
+  // Eq. (12): L' = (L v + alpha s) / (P + alpha)
+  const double da = block_sum<NT_VJP>(t < nA ? (double)lbp * (double)(sm.sc[t] - sm.lp[t]) / Dl : 0.0, sm.redd);
+  const float Pb = -block_sum<NT_VJP>(t < nA ? lbp * sm.lp[t] / Dl : 0.f, sm.redv);
+  dalpha += da;
+  if (t < nA) {
+    sm.vb[t] = lbp * sm.lt[t] / Dl;
+    sm.lb[t] = lbp * sm.v[t] / Dl;  // direct term; more below
+  }
+  if (t < nB) rbp += 2.f * Pb * sm.rp[t];
+  __syncthreads();
+  // v_a = sum_b R'_b R_b rho(a,b): y_b = sum_a vbar_a rho(a,b)
+  col_gather(sm, sm.vb, sm.rh, sm.tb, IdxClass{sm});
+  __syncthreads();
+  if (t < nB) {
+    rbp += sm.rt[t] * sm.tb[t];
+    sm.rb[t] = sm.rp[t] * sm.tb[t];
+    sm.rbp[t] = rbp;
+  }
+  // Eq. (13): R' = (R u + beta g) / (Q + beta)
+  const double db = block_sum<NT_VJP>(t < nB ? (double)rbp * (double)(sm.gc[t] - sm.rp[t]) / Dr : 0.0, sm.redd);
+  const float Qb = -block_sum<NT_VJP>(t < nB ? rbp * sm.rp[t] / Dr : 0.f, sm.redv);
+  dbeta += db;
+  if (t < nB) {
+    sm.ub[t] = rbp * sm.rt[t] / Dr;
+    sm.rb[t] += rbp * sm.u[t] / Dr;
+  }
+  if (t < nA) sm.lb[t] += 2.f * Qb * sm.lt[t];
+  __syncthreads();
+  // u_b = sum_a L_a^2 rho(a,b): z_a = sum_b ubar_b rho(a,b)
+  row_gather(sm, sm.ub, sm.rh, sm.ta, IdxClass{sm});
+  // rho-bar_m = sum over class m of vbar_a R'_b R_b + L_a^2 ubar_b
+  class_sums<true>(sm, sm.vb, sm.w, sm.l2, sm.ub, sm.rhb);
+  __syncthreads();
+  if (t < nA) sm.lb[t] += 2.f * sm.lt[t] * sm.ta[t];
+  // rho = s / d: d-bar = -rho-bar rho / d
+  sm.rhb[t] = sm.dcl[t] > 0.f ? -sm.rhb[t] * sm.rh[t] / sm.dcl[t] : 0.f;
+  __syncthreads();
+  // d_m = sum over class m of L_a R_b
+  row_gather(sm, sm.rt, sm.rhb, sm.ta, IdxClass{sm});
+  col_gather(sm, sm.lt, sm.rhb, sm.tb, IdxClass{sm});
+  __syncthreads();
+  if (t < nA) sm.lb[t] += sm.ta[t];
+  if (t < nB) sm.rb[t] += sm.tb[t];
+  __syncthreads();
+}
+
+// dtarget: dLoss/dh~ [n][256]; ckpt: dense (L, R) per checkpoint; writes
+// dalpha[i], dbeta[i].
+__global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const uint32_t* hg, SolveParams p,
+                                                      int ncp, const float* ckpt, const float* dtarget,
+                                                      double* dalpha, double* dbeta, uint32_t* flags) {
+  constexpr int BINS = DIFF_BINS;
+  __shared__ VjpSmem sm;
+  const int img = blockIdx.x, t = threadIdx.x;
+  const uint64_t N = solve_setup<BINS, NT_VJP>(hv + (size_t)img * BINS, hg + (size_t)img * BINS, -1, sm, flags);
+  const int nA = sm.nA, nB = sm.nB, E = p.ckpt_every;
+  const float* ck = ckpt + (size_t)img * ncp * 2 * BINS;
+  if (t < nA) {
+    const int a = sm.A[t];
+    sm.theta[t] = a ? pow((double)a / (double)(BINS - 1), p.inv_gamma) : 0.0;  // Eq. (17)
+  }
+  sm.gH[t] = dtarget[(size_t)img * BINS + t];
+  // final state
+  const float* last = ck + (size_t)(ncp - 1) * 2 * BINS;
+  if (t < nA) sm.lt[t] = last[sm.A[t]];
+  if (t < nB) sm.rt[t] = last[BINS + sm.B[t]];
+  __syncthreads();
+  // Eq. (20): h~_k = N sum over idx1(a,b) = k of L_a R_b
+  row_gather(sm, sm.rt, sm.gH, sm.ta, Idx1Class{sm});
+  col_gather(sm, sm.lt, sm.gH, sm.tb, Idx1Class{sm});
+  __syncthreads();
+  const float Nf = (float)N;
+  if (t < nA) sm.lb[t] = Nf * sm.ta[t];
+  if (t < nB) sm.rb[t] = Nf * sm.tb[t];
+  __syncthreads();
+  double da = 0.0, db = 0.0;
+  for (int seg = ncp - 2; seg >= 0; --seg) {
+    const float* c0 = ck + (size_t)seg * 2 * BINS;
+    if (t < nA) sm.segl[0][t] = c0[sm.A[t]];
+    if (t < nB) sm.segr[0][t] = c0[BINS + sm.B[t]];
+    __syncthreads();
+    // recompute the states of the segment
+    for (int q = 1; q < E; ++q) {
+      if (t < nA) sm.lt[t] = sm.segl[q - 1][t];
+      if (t < nB) sm.rt[t] = sm.segr[q - 1][t];
+      __syncthreads();
+      vjp_forward_pass(sm, p);
+      if (t < nA) sm.segl[q][t] = sm.lp[t] / sm.sc_Sl;
+      if (t < nB) sm.segr[q][t] = sm.rp[t] / sm.sc_Sr;
+      __syncthreads();
+    }
+    for (int q = E - 1; q >= 0; --q) {
+      if (t < nA) sm.lt[t] = sm.segl[q][t];
+      if (t < nB) sm.rt[t] = sm.segr[q][t];
+      __syncthreads();
+      vjp_forward_pass(sm, p);
+      vjp_backward_pass(sm, p, da, db);
+    }
+  }
+  if (t == 0) {
+    dalpha[img] = da;
+    dbeta[img] = db;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+namespace launch {
+
+hipError_t solve_ckpt(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, float* ckpt,
+                      float* target, uint32_t* lists, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_ckpt, dim3(n), dim3(NT_SOLVE), 0, s, hv, hg, p, ncp, ckpt, target, lists, flags);
+  return hipGetLastError();
+}
+
+hipError_t softmatch(int n, const ImgDesc* desc, int64_t max_npix, const uint32_t* hv, const float* target,
+                     float* m_tab, unsigned long long* acc, double* loss, float* dtarget, hipStream_t s) {
+  hipLaunchKernelGGL(k_softmap, dim3(n), dim3(DIFF_BINS), 0, s, hv, target, m_tab);
+  hipError_t e = fill_u32(reinterpret_cast<uint32_t*>(acc), (int64_t)n * (DIFF_BINS + 1) * 2, 0u, s);
+  if (e != hipSuccess) return e;
+  const int64_t tile_px = (int64_t)NT_PIX * 16 * 8;
+  const int64_t tiles = (max_npix + tile_px - 1) / tile_px;
+  hipLaunchKernelGGL(k_softloss, dim3((unsigned)tiles, n), dim3(NT_PIX), 0, s, desc, m_tab, tile_px, acc);
+  hipLaunchKernelGGL(k_softgrad, dim3(n), dim3(DIFF_BINS), 0, s, hv, target, acc, loss, dtarget);
+  return hipGetLastError();
+}
+
+hipError_t solve_vjp(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, const float* ckpt,
+                     const float* dtarget, double* dalpha, double* dbeta, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_vjp, dim3(n), dim3(NT_VJP), 0, s, hv, hg, p, ncp, ckpt, dtarget, dalpha, dbeta, flags);
+  return hipGetLastError();
+}
+
+int diff_seg_max() { return SEG_MAX; }
+
+}  // namespace launch
+}  // namespace hr

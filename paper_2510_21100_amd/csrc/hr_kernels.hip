@@ -45,14 +45,6 @@ __global__ __launch_bounds__(NT_PIX) void k_hist(ImgDesc d, int64_t tile_px, uin
   if (threadIdx.x == 0) *ticket = 0;  // ready for the next call
 }
 
-// LDS budgets of the solver: the one-image kernel may take most of a CU's
-// 160 KB; inside the batched kernel the solver shares the union with the
-// pixel-tile state and stays small enough for several workgroups per CU.
-constexpr int SOLVE_BUDGET_PLAIN = 150 * 1024;
-// solver scratch per image in global memory (32-bit words), as allocated by
-// the workspace: 3 * l^2
-template <int BINS> constexpr int64_t LIST_WORDS = 3LL * BINS * BINS;
-constexpr int NT_SOLVE = 1024;  // solver workgroup (one-image and batched kernels alike)
 constexpr int NT_BATCH = NT_SOLVE;
 // The batched kernel's register use allows one 512-thread workgroup per CU,
 // so its solver can take most of the CU's LDS as well.

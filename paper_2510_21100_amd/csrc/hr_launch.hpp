@@ -32,7 +32,7 @@ struct SolveParams {
   int32_t iters;
   float alpha;
   float beta;
-  int32_t pad;
+  int32_t ckpt_every;  // differentiated form: checkpoint interval (0: none)
   double inv_gamma;
 };
 
@@ -94,6 +94,14 @@ hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, Imag
 int step_px(int bits);
 int batch_step_px(int bits);
 int max_width(int bits);
+// differentiated form (256 levels)
+hipError_t solve_ckpt(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, float* ckpt,
+                      float* target, uint32_t* lists, uint32_t* flags, hipStream_t s);
+hipError_t softmatch(int n, const ImgDesc* desc, int64_t max_npix, const uint32_t* hv, const float* target,
+                     float* m_tab, unsigned long long* acc, double* loss, float* dtarget, hipStream_t s);
+hipError_t solve_vjp(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, const float* ckpt,
+                     const float* dtarget, double* dalpha, double* dbeta, uint32_t* flags, hipStream_t s);
+int diff_seg_max();
 }  // namespace launch
 
 }  // namespace hr
