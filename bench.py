@@ -94,6 +94,59 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _gen_truth(args):
+    cfg, n, i, h, w = args
+    img, rho = make_image(config_seed(cfg, n, i), h, w, return_truth=True)
+    return img, (0.8 * rho).astype(np.float32)
+
+
+DIFF_DESC = ("32 RGB uint8 1000x664 images against 0.8 x their reflectance (FP32 HWC), 256 bins, "
+             "K = 30 unrolled iterations, checkpoints every 5")
+
+
+def time_diff(dev, steps: int, workers: int):
+    """Forward and forward+backward of the differentiated form on 32 images of
+    1000x664 (gradients with respect to alpha, beta and the target histogram)."""
+    import torch
+
+    from paper_2510_21100_amd import api, diff
+
+    n, (h, w) = 32, (664, 1000)
+    jobs = [(5, n, i, h, w) for i in range(n)]
+    if workers > 1:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            pairs = list(ex.map(_gen_truth, jobs))
+    else:
+        pairs = [_gen_truth(j) for j in jobs]
+    imgs = [torch.from_numpy(a).to(dev) for a, _ in pairs]
+    tims = [torch.from_numpy(t).to(dev) for _, t in pairs]
+    ws = api.Workspace(max_images=n, max_bins=256)
+
+    def run(backward: bool):
+        alpha = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        beta = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        loss, target = diff.enhancement_loss(imgs, tims, alpha, beta, iters=30, ckpt_every=5, ws=ws)
+        if backward:
+            loss.backward()
+        return loss
+
+    out = {}
+    for name, bw in (("forward", False), ("forward_backward", True)):
+        run(bw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run(bw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name + "_ms"] = round(ms, 3)
+    npix = n * h * w
+    out.update({"workload": DIFF_DESC, "pixels": npix,
+                "Mpix_per_s_forward_backward": round(npix / (out["forward_backward_ms"] * 1e-3) / 1e6, 1)})
+    ws.close()
+    return out
+
+
 def generate(jobs, workers: int):
     if len(jobs) == 1 or workers <= 1:
         return [_gen(j) for j in jobs]
@@ -180,6 +233,7 @@ def main():
     ap.add_argument("--remap-steps", type=int, default=0)
     ap.add_argument("--schedule", default=os.path.join(ROOT, "paper_2510_21100_amd", "schedule.json"))
     ap.add_argument("--no-plain", action="store_true", help="skip the one-image form and the solver timing")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiated-form timing")
     ap.add_argument("--device-warmup-s", type=float, default=0.3,
                     help="seconds of untimed batched calls before the warmup steps")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -264,6 +318,10 @@ def main():
     plain_ms = plain_value = solve_us = None
     if not args.no_plain:
         plain_ms, plain_value, solve_us = time_plain(H, gimgs, outs, params, bins, stream, args.plain_steps)
+    diff_line = None
+    if not args.no_plain and not args.no_diff:
+        diff_line = time_diff(dev, 3, args.workers)
+
     cpu = None
     if args.cpu_budget > 0:
         cpu = cpu_baseline(imgs, bits, args.cpu_budget)
@@ -306,6 +364,7 @@ def main():
             "batched_over_plain": round(value / plain_value, 3),
             "form": "one image per call: hr_build_hist, hr_solve, hr_match launched per image"},
         "solve_us_per_image": None if solve_us is None else round(solve_us, 1),
+        "differentiated": diff_line,
         "gen_seconds": round(gen_s, 1),
         "device_warmup_calls": n_w,
         "cpu_baseline": cpu,

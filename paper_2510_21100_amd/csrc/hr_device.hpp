@@ -821,6 +821,7 @@ struct SolveCore {
   alignas(16) float l2c[BINS + PAD];                // L^2 on A (zero padded), later L'
   alignas(16) float wc[BINS + PAD];                 // R' R on B (zero padded)
   float rn[BINS];                                   // R' of Eq. (13) on B
+  double rcum[BINS + 1];                            // running sums of R on B (sweeps without a list)
   float sd[BINS];                                   // s by level (dense)
   float inv2a[BINS];                                // 1 / (2a) for the rows of A
   alignas(8) float rho[BINS + 4];                   // s_m / d_m by class
@@ -832,6 +833,7 @@ struct SolveCore {
   int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
   float redf[4][NT / 64];
   uint64_t redu[NT / 64];
+  double redd[NT / 64];
   int32_t redi[NT / 64];
   int32_t nA, nB, nc, C, CS, R, nAp, nBp;           // CS: cell stride of a chunk
   int32_t cells_lds, tab_lds, use_list;
@@ -1175,18 +1177,24 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
             sm.rho[cls] = acc > 0.f ? sm.sd[cls] / acc : 0.f;
         }
       } else {
-        // one class per lane: rows of A, each contributing a run of B
-        for (int m = t; m < BINS; m += NT) {
-          if (sm.sd[m] <= 0.f) continue;
-          float d = 0.f;
-          for (int i = sm.PA[m]; i < nA; ++i) {
+        // one class per lane: rows of A, each contributing a run of B, summed
+        // as a difference of FP64 running sums of R (O(1) per run)
+        for (int j = t; j <= nB; j += NT) sm.rcum[j] = j < nB ? (double)sm.rc[j] : 0.0;
+        __syncthreads();
+        block_scan<NT, double>(sm.rcum, nB + 1, sm.redd);
+        // only the classes of occupied levels (s_m > 0, i.e. m in A) are
+        // needed; each gets Gd consecutive lanes taking every Gd-th row
+        const int Gd = pow2_floor64(max(1, NT / nA));
+        for (int q = t; q < nA * Gd; q += NT) {
+          const int m = sm.A[q / Gd], k = q & (Gd - 1);
+          double d = 0.0;
+          for (int i = sm.PA[m] + k; i < nA; i += Gd) {
             int jlo, jhi;
             class_run<BINS>(sm, i, m, jlo, jhi);
-            float run = 0.f;
-            for (int j = jlo; j < jhi; ++j) run += sm.rc[j];
-            d = fmaf(sm.lc[i], run, d);
+            if (jhi > jlo) d = fma((double)sm.lc[i], sm.rcum[jhi] - sm.rcum[jlo], d);
           }
-          sm.rho[m] = d > 0.f ? sm.sd[m] / d : 0.f;
+          for (int w = Gd >> 1; w >= 1; w >>= 1) d += __shfl_xor(d, w, 64);
+          if (k == 0) sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] / d) : 0.f;
         }
       }
       float ql = 0.f;
@@ -1222,8 +1230,13 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         } else {
           const int b = sm.B[o];
-          for (int s = s0; s < s0 + Lc; ++s)
-            acc = fmaf(sm.l2c[s], sm.rho[class_of<BINS>(sm.A[min(s, nA - 1)], b)], acc);
+          float a4[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int s = s0; s < s0 + Lc; s += 4) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              a4[x] = fmaf(sm.l2c[s + x], sm.rho[class_of<BINS>(sm.A[min(s + x, nA - 1)], b)], a4[x]);
+          }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
         for (int w = Gc >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
         if (k == 0 && q / Gc < nB) {
@@ -1263,8 +1276,13 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         } else {
           const int a = sm.A[o];
-          for (int s = s0; s < s0 + Lr; ++s)
-            acc = fmaf(sm.wc[s], sm.rho[class_of<BINS>(a, sm.B[min(s, nB - 1)])], acc);
+          float a4[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int s = s0; s < s0 + Lr; s += 4) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+              a4[x] = fmaf(sm.wc[s + x], sm.rho[class_of<BINS>(a, sm.B[min(s + x, nB - 1)])], a4[x]);
+          }
+          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
         for (int w = Gr >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
         if (k == 0 && q / Gr < nA) {
