@@ -312,7 +312,13 @@ struct HistSmem {
   static constexpr int BINS = Cfg<BITS>::BINS;
   static constexpr int REP = BITS == 8 ? (NT >= 512 ? 16 : 4) : (NT >= 512 ? 4 : 1);
   static constexpr int STRIDE = REP;
-  static constexpr int RING = pow2_at_least(MaxWidth<BITS>::value + 2 * Pix<BITS, NT>::STEP);
+  // 1024-thread workgroups split into a loading and a gradient half (see
+  // HistTileSplit), whose steps are STEPH pixels and lie up to
+  // 1 + ceil((W+1)/STEPH) steps apart; smaller ones alternate the two phases
+  static constexpr int STEPH = Pix<BITS, (NT >= 1024 ? NT / 2 : NT)>::STEP;
+  static constexpr int RING =
+      NT >= 1024 ? pow2_at_least(STEPH * (2 + (MaxWidth<BITS>::value + STEPH) / STEPH))
+                 : pow2_at_least(MaxWidth<BITS>::value + 2 * Pix<BITS, NT>::STEP);
   using pix_t = typename Cfg<BITS>::pix_t;
   static constexpr int RING_BYTES = RING * (int)sizeof(pix_t);
   uint32_t hs[BINS * STRIDE];
@@ -372,7 +378,7 @@ __device__ inline uint32_t grad_l1(uint32_t a, uint32_t b, uint32_t c) {
 // would leave the range re-reading chunk 0 of the image instead (in bounds:
 // the vector paths require at least one full chunk).  Partial steps go to a
 // tail with the same arithmetic.
-constexpr int PREFETCH = 2;
+constexpr int PREFETCH = 4;
 
 // V of the PX pixels of a chunk from its NW words
 template <int BITS, int PX, int NW>
@@ -554,6 +560,185 @@ struct HistTile {
   }
 };
 
+// Histogram tile for 1024-thread workgroups: the first half of the waves
+// (producers) stream the load steps into the ring and count V, the second
+// half (consumers) form the gradient of the step `lag` steps behind, so the
+// memory-bound and the LDS-bound halves of the work overlap; one barrier per
+// step.  Each half works like a 512-thread workgroup (Pix<BITS, NT/2>).  The
+// consumer's rows (its step, one row below it and one pixel further) were
+// written in earlier steps, and the producer's current step overwrites only
+// ring slots older than the consumer's step (the ring holds lag + 1 steps).
+template <int BITS, int NT>
+struct HistTileSplit {
+  static constexpr int NH = NT / 2;
+  using pix_t = typename Cfg<BITS>::pix_t;
+  using SM = HistSmem<BITS, NT>;
+  static constexpr int BINS = Cfg<BITS>::BINS, REP = SM::REP, SD = SM::STRIDE;
+  static constexpr int PX = Pix<BITS, NH>::PX, NW = Pix<BITS, NH>::NW, NV = Pix<BITS, NH>::NV;
+  static constexpr int STEP = Pix<BITS, NH>::STEP;
+  static constexpr int RING = SM::RING, RING_BYTES = SM::RING_BYTES;
+  static constexpr int ESZ = (int)sizeof(pix_t);
+  static constexpr int64_t CB = 3 * ESZ;
+  static_assert(RING >= STEP * (2 + (MaxWidth<BITS>::value + STEP) / STEP), "ring too small for the lag");
+
+  const ImgDesc& d;
+  SM& sm;
+  const int64_t P0, P1, N, E;
+  const int W, tt, step_mod_w;
+  const bool producer;
+  uint32_t* hs;
+  uint32_t* hg;
+  int x;
+  uint32_t clamped = 0;
+
+  __device__ HistTileSplit(const ImgDesc& d_, int64_t p0, int64_t p1, SM& sm_)
+      : d(d_), sm(sm_), P0(p0), P1(p1), N(d_.npix), E(min(p1 + (int64_t)d_.W, d_.npix)), W(d_.W),
+        tt(threadIdx.x & (NH - 1)), step_mod_w(STEP % d_.W), producer(threadIdx.x < NH),
+        hs(sm_.hs + (threadIdx.x & (REP - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))) {
+    x = (int)((P0 + (int64_t)tt * PX) % W);
+  }
+
+  __device__ const uint8_t* chunk_or_first(int64_t at) const {
+    const int64_t p = at + (int64_t)tt * PX;
+    return d.in + (p + PX <= E ? p : 0) * CB;
+  }
+
+  // producer: load step starting at `at` into the ring, V histogram below P1
+  __device__ void load_step(int64_t at, const uint32_t (&w)[NW], bool have) {
+    const int64_t p = at + (int64_t)tt * PX;
+    const int n = (int)max((int64_t)0, min((int64_t)PX, E - p));
+    if (n <= 0) return;
+    uint32_t v[PX];
+    if (have) values_of_words<BITS, PX, NW>(w, v, clamped);
+    else load_values<BITS, NH>(d, p, n, v, clamped);
+    uint32_t packed[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) packed[q] = 0;
+#pragma unroll
+    for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
+    const uint32_t boff = (uint32_t)(((p - P0) & (RING - 1)) * ESZ);
+    ring_write<NV>(sm.ring, boff, packed);
+    if (boff < 64) ring_write<NV>(sm.ring, RING_BYTES + boff, packed);
+    lds_wait();  // the ring stores are done before this wave's barrier
+    const int64_t nh = P1 - p;
+    if (nh >= PX) {
+#pragma unroll
+      for (int i = 0; i < PX; ++i) atomicAdd(&hs[v[i] * SD], 1u);
+    } else {
+#pragma unroll
+      for (int i = 0; i < PX; ++i)
+        if (i < nh) atomicAdd(&hs[v[i] * SD], 1u);
+    }
+  }
+
+  // consumer: gradient of the pixels [at, min(at + STEP, P1))
+  __device__ void grad_step(int64_t at) {
+    const int64_t dend = min(at + STEP, P1);
+    const int64_t q = at + (int64_t)tt * PX;
+    const int n = (int)max((int64_t)0, min((int64_t)PX, dend - q));
+    if (n > 0) {
+      const uint32_t boff = (uint32_t)(((q - P0) & (RING - 1)) * ESZ);
+      uint32_t own[NV];
+      ring_read<NV>(sm.ring, boff, own);
+      const uint32_t rboff = boff + PX * ESZ;
+      const uint32_t right_last = ESZ == 1 ? (uint32_t)reinterpret_cast<const uint8_t*>(sm.ring)[rboff]
+                                           : (uint32_t)reinterpret_cast<const uint16_t*>(sm.ring)[rboff >> 1];
+      const uint32_t dboff = (uint32_t)(((q + W - P0) & (RING - 1)) * ESZ);
+      uint32_t dn[NV];
+      ring_read<NV>(sm.ring, dboff, dn);
+      if (n == PX && N - W - q >= PX && W > PX) {
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+          const uint32_t vv = lane_of<pix_t>(own, i);
+          const uint32_t vr = (i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last;
+          atomicAdd(&hg[grad_l1(vr, vv, lane_of<pix_t>(dn, i)) * SD], 1u);
+        }
+        const int e = W - 1 - x;
+        if (e < PX) {
+          const uint32_t ve = lane_dyn<pix_t>(own, e);
+          const uint32_t vre = (e + 1 < PX) ? lane_dyn<pix_t>(own, e + 1) : right_last;
+          const uint32_t vde = lane_dyn<pix_t>(dn, e);
+          atomicSub(&hg[grad_l1(vre, ve, vde) * SD], 1u);
+          atomicAdd(&hg[grad_l1(ve, ve, vde) * SD], 1u);
+        }
+      } else {
+        int xx = x;
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+          if (i < n) {
+            const uint32_t vv = lane_of<pix_t>(own, i);
+            const uint32_t vr = (xx + 1 < W) ? ((i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last) : vv;
+            const uint32_t vd = (q + i + W < N) ? lane_of<pix_t>(dn, i) : vv;
+            atomicAdd(&hg[grad_l1(vr, vv, vd) * SD], 1u);
+            if (++xx == W) xx = 0;
+          }
+        }
+      }
+    }
+    x += step_mod_w;
+    if (x >= W) x -= W;
+  }
+
+  __device__ void run() {
+    const int64_t nload = (E - P0 + STEP - 1) / STEP;   // load steps with pixels
+    const int64_t ngrad = (P1 - P0 + STEP - 1) / STEP;  // gradient steps
+    const int64_t lag = 1 + (W + STEP) / STEP;          // 1 + ceil((W + 1) / STEP)
+    const int64_t K = lag + ngrad;                      // iterations (covers nload)
+    int64_t k = 0;
+    if (d.in_vec && N >= PX) {
+      const int64_t nfull = (E - P0) / STEP;  // load steps whose chunks are all full
+      uint32_t buf[PREFETCH][NW];
+      if (producer) {
+#pragma unroll
+        for (int j = 0; j < PREFETCH; ++j) load_words<NW, false>(chunk_or_first(P0 + (int64_t)j * STEP), buf[j]);
+      }
+      while (k + PREFETCH <= nfull) {
+#pragma unroll
+        for (int kk = 0; kk < PREFETCH; ++kk) {
+          if (producer) {
+            load_step(P0 + k * STEP, buf[kk], true);
+            load_words<NW, false>(chunk_or_first(P0 + (k + PREFETCH) * STEP), buf[kk]);
+          } else if (k >= lag) {
+            grad_step(P0 + (k - lag) * STEP);
+          }
+          bare_barrier();
+          ++k;
+        }
+      }
+      while (k < K) {
+#pragma unroll
+        for (int kk = 0; kk < PREFETCH; ++kk) {
+          if (k < K) {  // uniform
+            if (producer) {
+              if (k < nload) {
+                const int64_t p = P0 + k * STEP + (int64_t)tt * PX;
+                load_step(P0 + k * STEP, buf[kk], p + PX <= E);
+              }
+              load_words<NW, false>(chunk_or_first(P0 + (k + PREFETCH) * STEP), buf[kk]);
+            } else if (k >= lag) {
+              grad_step(P0 + (k - lag) * STEP);
+            }
+            bare_barrier();
+            ++k;
+          }
+        }
+      }
+    } else {
+      uint32_t none[NW];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) none[q] = 0;
+      for (; k < K; ++k) {
+        if (producer) {
+          if (k < nload) load_step(P0 + k * STEP, none, false);
+        } else if (k >= lag) {
+          grad_step(P0 + (k - lag) * STEP);
+        }
+        bare_barrier();
+      }
+    }
+  }
+};
+
 template <int BITS, int NT>
 __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BITS, NT>& sm,
                           uint32_t* __restrict__ g_hs, uint32_t* __restrict__ g_graw) {
@@ -564,9 +749,16 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
   for (int i = t; i < (2 * BINS - 1) * SD; i += NT) sm.hg[i] = 0;
   if (t == 0) sm.clamped = 0;
   __syncthreads();
-  HistTile<BITS, NT> ht(d, P0, P1, sm);
-  ht.run();
-  const uint32_t clamped = ht.clamped;
+  uint32_t clamped;
+  if constexpr (NT >= 1024) {
+    HistTileSplit<BITS, NT> ht(d, P0, P1, sm);
+    ht.run();
+    clamped = ht.clamped;
+  } else {
+    HistTile<BITS, NT> ht(d, P0, P1, sm);
+    ht.run();
+    clamped = ht.clamped;
+  }
   if (clamped) atomicOr(&sm.clamped, 1u);
   __syncthreads();
   for (int k = t; k < BINS; k += NT) {
