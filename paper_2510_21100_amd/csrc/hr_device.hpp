@@ -96,11 +96,79 @@ __device__ inline void set_lane(uint32_t (&w)[N], int k, uint32_t v) {
   }
 }
 
+// Cross-lane moves through DPP (a VALU operand modifier, no LDS round trip).
+// Controls in the gfx9 encoding: row_shr:n shifts within rows of 16 lanes,
+// row_bcast:15 / row_bcast:31 pass lane 15 of each row (lane 31) to the rows
+// that the row mask enables.  Lanes without a source read zero.
+namespace dpp {
+constexpr int ROW_SHR = 0x110;  // + n, n = 1..15
+constexpr int BCAST15 = 0x142;
+constexpr int BCAST31 = 0x143;
+}  // namespace dpp
+
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, true);
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ inline T dpp_get(T x) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, dpp32<CTRL, ROWS>(__builtin_bit_cast(uint32_t, x)));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = dpp32<CTRL, ROWS>((uint32_t)u), hi = dpp32<CTRL, ROWS>((uint32_t)(u >> 32));
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
+
+template <typename T>
+__device__ inline T read_lane(T x, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
+
+// Inclusive prefix sum over the 64 lanes of the wave (all lanes active).
+template <typename T>
+__device__ inline T wave_scan(T x) {
+  x += dpp_get<dpp::ROW_SHR + 1, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 2, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 4, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 8, 0xf>(x);
+  x += dpp_get<dpp::BCAST15, 0xa>(x);
+  x += dpp_get<dpp::BCAST31, 0xc>(x);
+  return x;
+}
+
+// Sums over aligned groups of G lanes (G a power of two, 1..64), complete in
+// the last lane of each group (other lanes hold partial sums).
+template <typename T>
+__device__ inline T group_sum_last(T x, int G) {
+  const int p = threadIdx.x & 63, r = p & (G - 1);
+  T y;
+  y = dpp_get<dpp::ROW_SHR + 1, 0xf>(x);
+  if (r >= 1) x += y;
+  y = dpp_get<dpp::ROW_SHR + 2, 0xf>(x);
+  if (r >= 2) x += y;
+  y = dpp_get<dpp::ROW_SHR + 4, 0xf>(x);
+  if (r >= 4) x += y;
+  y = dpp_get<dpp::ROW_SHR + 8, 0xf>(x);
+  if (r >= 8) x += y;
+  if (G >= 32) x += dpp_get<dpp::BCAST15, 0xa>(x);
+  if (G >= 64) x += dpp_get<dpp::BCAST31, 0xc>(x);
+  return x;
+}
+
 template <typename T>
 __device__ inline T wave_sum(T x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  return read_lane(wave_scan(x), 63);
 }
 
 template <typename T>
@@ -149,12 +217,7 @@ __device__ inline T block_scan(T* arr, int n, T* red) {
   for (int i = b0; i < b1; ++i) local += arr[i];
   // inclusive scan of the per-thread totals over the wave
   const int lane = t & 63;
-  T inc = local;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    T y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
-  }
+  const T inc = wave_scan(local);
   __syncthreads();
   if (lane == 63) red[t >> 6] = inc;
   __syncthreads();
@@ -1012,7 +1075,8 @@ struct SolveCore {
   float lc[BINS + 4], rc[BINS + 4];                 // current L on A, R on B; [n] = 0
   alignas(16) float l2c[BINS + PAD];                // L^2 on A (zero padded), later L'
   alignas(16) float wc[BINS + PAD];                 // R' R on B (zero padded)
-  float rn[BINS];                                   // R' of Eq. (13) on B
+  float lraw[BINS + 4];                             // L' of Eq. (12) on A, before Eq. (15); [n] = 0
+  float rn[BINS + 4];                               // R' of Eq. (13) on B, before Eq. (14); [n] = 0
   double rcum[BINS + 1];                            // running sums of R on B (sweeps without a list)
   float sd[BINS];                                   // s by level (dense)
   float inv2a[BINS];                                // 1 / (2a) for the rows of A
@@ -1084,10 +1148,31 @@ __device__ inline void class_run(const SM& sm, int i, int m, int& jlo, int& jhi)
   jhi = sm.PB[bhi + 1];
 }
 
+// class_run for a row with a >= m, as in the class sweep.  There
+// (2m +- 1)(l-1) / 2a lies below 1.5 (l-1) and at least 1/2a from an
+// integer, and the FP32 product with the rounded reciprocal is within
+// 2^-23 relative, under 2e-4: truncation is the exact floor, no correction
+// (checked for every a and m <= a at l = 256 and 1024).
+template <int BINS, typename SM>
+__device__ inline void class_run_upper(const SM& sm, int i, int m, int& jlo, int& jhi) {
+  constexpr uint32_t D = BINS - 1;
+  const int a = sm.A[i];
+  if (a == 0) {  // m = 0: the whole row
+    jlo = 0;
+    jhi = sm.nB;
+    return;
+  }
+  const float inv = sm.inv2a[i];
+  const uint32_t blo = m == 0 ? 0u : (uint32_t)((float)((2u * m - 1u) * D) * inv) + 1u;
+  const uint32_t bhi = min((uint32_t)((float)((2u * m + 1u) * D) * inv), (uint32_t)(BINS - 1));
+  jlo = sm.PB[blo];
+  jhi = sm.PB[max(bhi + 1u, blo)];  // blo > bhi: empty
+}
+
 template <int NT>
 __device__ inline void wave_partial(float x, float* red) {
-  x = wave_sum(x);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  x = wave_scan(x);
+  if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = x;
 }
 
 template <int NT>
@@ -1292,11 +1377,57 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
 
 // Dense copy of the current (L, R) into state[0..2 BINS): level k of L at
 // [k], of R at [BINS + k], 0 at unoccupied levels.
+// Lanes of the class sweep without a list.  Class q (level A[q]) collects
+// the rows q..nA-1 (a >= A[q]; lower rows never reach class A[q]), so the
+// classes carry nA, nA-1, ..., 1 rows.  With at most c rows per lane, class q
+// gets ceil((nA - q) / c) consecutive lanes; c is the smallest value for
+// which all classes fit in NT lanes (c = 1 when nA (nA + 1) / 2 <= NT).
+struct ClassLanes {
+  int q, k, g;  // class index (-1: idle lane), lane within the class, lanes of the class
+};
+
+// sum_{w=1..n} ceil(w / c)
+__device__ inline int lanes_upto(int n, int c) {
+  const int k = n / c, r = n - k * c;
+  return c * (k * (k + 1) / 2) + r * (k + 1);
+}
+
+template <int NT>
+__device__ inline ClassLanes class_lanes(int nA, int t) {
+  ClassLanes r{-1, 0, 1};
+  if (nA <= 0) return r;
+  int lo = 1, hi = nA;  // lanes_upto(nA, nA) = nA <= NT
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (lanes_upto(nA, mid) <= NT)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int c = lo, total = lanes_upto(nA, c);
+  if (t >= total) return r;
+  // first lane of class q: total - lanes_upto(nA - q, c), increasing in q
+  int a = 0, b = nA - 1;
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (total - lanes_upto(nA - mid, c) <= t)
+      a = mid;
+    else
+      b = mid - 1;
+  }
+  r.q = a;
+  r.k = t - (total - lanes_upto(nA - a, c));
+  r.g = (nA - a + c - 1) / c;
+  return r;
+}
+
+// Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
+// the values the next pass works with.
 template <int BINS, int NT>
-__device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state) {
+__device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, float sumL, float sumR) {
   for (int k = threadIdx.x; k < BINS; k += NT) {
-    state[k] = sm.sd[k] > 0.f ? sm.lc[sm.PA[k]] : 0.f;
-    state[BINS + k] = sm.PB[k + 1] > sm.PB[k] ? sm.rc[sm.PB[k]] : 0.f;
+    state[k] = sm.sd[k] > 0.f ? sm.lraw[sm.PA[k]] / sumL : 0.f;
+    state[BINS + k] = sm.PB[k + 1] > sm.PB[k] ? sm.rn[sm.PB[k]] / sumR : 0.f;
   }
 }
 
@@ -1310,6 +1441,8 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   constexpr int SH = CellT<BINS>::SHIFT;
   constexpr uint32_t MASK = (1u << SH) - 1;
   constexpr int PAD = SolveCore<BINS, NT>::PAD;
+  static_assert(BINS <= NT, "one lane per class at least");
+  static_assert(SolveSmem<BINS, NT, BUDGET>::FREE >= 8 * NT, "lane partials of the class sweep");
   const int t = threadIdx.x, lane = t & 63;
   const int nA = sm.nA, nB = sm.nB, C = sm.C, CS = sm.CS, R = sm.R;
   const cell_t* cells = CELLS_LDS ? cell_store(sm) : gcells;
@@ -1326,16 +1459,30 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     if (q >= nB) sm.wc[q] = 0.f;
   }
   for (int m = t; m < BINS + 4; m += NT) sm.rho[m] = 0.f;
+  // the passes start from L' = L(0), R' = R(0) with unit sums (Eqs. 14, 15
+  // are folded into the next pass's class sweep)
+  for (int i = t; i <= nA; i += NT) sm.lraw[i] = i < nA ? sm.lc[i] : 0.f;
+  for (int j = t; j <= nB; j += NT) sm.rn[j] = j < nB ? sm.rc[j] : 0.f;
+  for (int w = t; w < NT / 64; w += NT) {
+    sm.redf[2][w] = w == 0 ? 1.f : 0.f;
+    sm.redf[3][w] = w == 0 ? 1.f : 0.f;
+  }
   if (t == 0) {
     sm.lc[nA] = 0.f;
     sm.rc[nB] = 0.f;
   }
+  const ClassLanes cl = LIST ? ClassLanes{-1, 0, 1} : class_lanes<NT>(nA, t);
   __syncthreads();
 
   for (int it = 0; it < p.iters; ++it) {
-    if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0) write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS);
-    // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m
+    // sums of the previous pass's L', R' (Eqs. 14, 15)
+    const float sumL = block_read<NT>(sm.redf[3]), sumR = block_read<NT>(sm.redf[2]);
+    if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0)
+      write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS, sumL, sumR);
+    // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m, from the
+    // unnormalised L', R': d_m = (sum of L' R' over the class) / (sumL sumR)
     {
+      const float sLR = sumL * sumR;
       if constexpr (LIST) {
         // one chunk per lane and round; a class is summed inside its wave
         for (int r = 0; r < R; ++r) {
@@ -1355,46 +1502,73 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
               e[0] = w.x; e[1] = w.y; e[2] = w.z; e[3] = w.w;
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x) a4[x] = fmaf(sm.lc[e[x] & MASK], sm.rc[e[x] >> SH], a4[x]);
+            for (int x = 0; x < 4; ++x) a4[x] = fmaf(sm.lraw[e[x] & MASK], sm.rn[e[x] >> SH], a4[x]);
           }
           float acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
           const int cls = sm.chunk_cls[u];
           const int seg0 = cls >= 0 ? (sm.off[cls] & 63) : 64;  // lane of the class's first chunk
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {  // inclusive segmented scan over the class's lanes
-            const float y = __shfl_up(acc, o, 64);
-            if (lane - o >= seg0) acc += y;
+          {  // inclusive segmented scan over the class's lanes
+            float y;
+            y = dpp_get<dpp::ROW_SHR + 1, 0xf>(acc);
+            if (lane - 1 >= seg0) acc += y;
+            y = dpp_get<dpp::ROW_SHR + 2, 0xf>(acc);
+            if (lane - 2 >= seg0) acc += y;
+            y = dpp_get<dpp::ROW_SHR + 4, 0xf>(acc);
+            if (lane - 4 >= seg0) acc += y;
+            y = dpp_get<dpp::ROW_SHR + 8, 0xf>(acc);
+            if (lane - 8 >= seg0) acc += y;
+            y = dpp_get<dpp::BCAST15, 0xa>(acc);  // rows 1, 3 from lanes 15, 47
+            if ((lane & ~15) - 1 >= seg0) acc += y;
+            y = dpp_get<dpp::BCAST31, 0xc>(acc);  // rows 2, 3 from lane 31
+            if (31 >= seg0) acc += y;
           }
           if (cls >= 0 && (u - sm.off[cls] + 1) * C >= sm.csz[cls])
-            sm.rho[cls] = acc > 0.f ? sm.sd[cls] / acc : 0.f;
+            sm.rho[cls] = acc > 0.f ? sm.sd[cls] * sLR / acc : 0.f;
         }
       } else {
-        // one class per lane: rows of A, each contributing a run of B, summed
-        // as a difference of FP64 running sums of R (O(1) per run)
-        for (int j = t; j <= nB; j += NT) sm.rcum[j] = j < nB ? (double)sm.rc[j] : 0.0;
+        // rows of A, each contributing a run of B, summed as a difference of
+        // FP64 running sums of R (O(1) per run); only the classes of occupied
+        // levels (s_m > 0, i.e. m in A) are needed.  Lanes as in cl: the
+        // rows of a class are dealt round-robin over its lanes, two at a time
+        for (int j = t; j <= nB; j += NT) sm.rcum[j] = j < nB ? (double)sm.rn[j] : 0.0;
         __syncthreads();
         block_scan<NT, double>(sm.rcum, nB + 1, sm.redd);
-        // only the classes of occupied levels (s_m > 0, i.e. m in A) are
-        // needed; each gets Gd consecutive lanes taking every Gd-th row
-        const int Gd = pow2_floor64(max(1, NT / nA));
-        for (int q = t; q < nA * Gd; q += NT) {
-          const int m = sm.A[q / Gd], k = q & (Gd - 1);
-          double d = 0.0;
-          for (int i = sm.PA[m] + k; i < nA; i += Gd) {
-            int jlo, jhi;
-            class_run<BINS>(sm, i, m, jlo, jhi);
-            if (jhi > jlo) d = fma((double)sm.lc[i], sm.rcum[jhi] - sm.rcum[jlo], d);
+        double d0 = 0.0, d1 = 0.0;
+        if (cl.q >= 0) {
+          const int m = sm.A[cl.q], g = cl.g;
+          int i = cl.q + cl.k;
+          for (; i + g < nA; i += 2 * g) {
+            int jlo0, jhi0, jlo1, jhi1;
+            class_run_upper<BINS>(sm, i, m, jlo0, jhi0);
+            class_run_upper<BINS>(sm, i + g, m, jlo1, jhi1);
+            // an empty run has jlo = jhi and adds an exact zero
+            d0 = fma((double)sm.lraw[i], sm.rcum[jhi0] - sm.rcum[jlo0], d0);
+            d1 = fma((double)sm.lraw[i + g], sm.rcum[jhi1] - sm.rcum[jlo1], d1);
           }
-          for (int w = Gd >> 1; w >= 1; w >>= 1) d += __shfl_xor(d, w, 64);
-          if (k == 0) sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] / d) : 0.f;
+          if (i < nA) {
+            int jlo, jhi;
+            class_run_upper<BINS>(sm, i, m, jlo, jhi);
+            d0 = fma((double)sm.lraw[i], sm.rcum[jhi] - sm.rcum[jlo], d0);
+          }
+        }
+        double* part = reinterpret_cast<double*>(sm.spare);  // NT lane partials
+        part[t] = d0 + d1;
+        __syncthreads();
+        if (cl.q >= 0 && cl.k == 0) {
+          double d = 0.0;
+          for (int x = 0; x < cl.g; ++x) d += part[t + x];
+          const int m = sm.A[cl.q];
+          sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d) : 0.f;
         }
       }
       float ql = 0.f;
       for (int i = t; i < nA; i += NT) {
-        const float l = sm.lc[i];
+        const float l = sm.lraw[i] / sumL;  // Eq. (15)
+        sm.lc[i] = l;
         sm.l2c[i] = l * l;
         ql += l * l;
       }
+      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;  // Eq. (14)
       wave_partial<NT>(ql, sm.redf[0]);
     }
     __syncthreads();
@@ -1423,15 +1597,18 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         } else {
           const int b = sm.B[o];
           float a4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
           for (int s = s0; s < s0 + Lc; s += 4) {
+            const v4u xv = *reinterpret_cast<const v4u*>(&sm.l2c[s]);
+            const uint32_t x4[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
             for (int x = 0; x < 4; ++x)
-              a4[x] = fmaf(sm.l2c[s + x], sm.rho[class_of<BINS>(sm.A[min(s + x, nA - 1)], b)], a4[x]);
+              a4[x] = fmaf(__uint_as_float(x4[x]), sm.rho[class_of<BINS>(sm.A[min(s + x, nA - 1)], b)], a4[x]);
           }
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
-        for (int w = Gc >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
-        if (k == 0 && q / Gc < nB) {
+        acc = group_sum_last(acc, Gc);
+        if (k == Gc - 1 && q / Gc < nB) {
           const float r = sm.rc[o];
           const float rn = (r * acc + p.beta * sm.gc[o]) / denR;
           sm.rn[o] = rn;
@@ -1469,34 +1646,36 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         } else {
           const int a = sm.A[o];
           float a4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
           for (int s = s0; s < s0 + Lr; s += 4) {
+            const v4u xv = *reinterpret_cast<const v4u*>(&sm.wc[s]);
+            const uint32_t x4[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
             for (int x = 0; x < 4; ++x)
-              a4[x] = fmaf(sm.wc[s + x], sm.rho[class_of<BINS>(a, sm.B[min(s + x, nB - 1)])], a4[x]);
+              a4[x] = fmaf(__uint_as_float(x4[x]), sm.rho[class_of<BINS>(a, sm.B[min(s + x, nB - 1)])], a4[x]);
           }
           acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
         }
-        for (int w = Gr >> 1; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
-        if (k == 0 && q / Gr < nA) {
+        acc = group_sum_last(acc, Gr);
+        if (k == Gr - 1 && q / Gr < nA) {
           const float ln = (sm.lc[o] * acc + p.alpha * sm.sc[o]) / denL;
-          sm.l2c[o] = ln;
+          sm.lraw[o] = ln;
           sl += ln;
         }
       }
       wave_partial<NT>(sl, sm.redf[3]);
     }
     __syncthreads();
-    // Eqs. (15), (14): rescale to unit mass
-    {
-      const float sumL = block_read<NT>(sm.redf[3]);
-      const float sumR = block_read<NT>(sm.redf[2]);
-      for (int i = t; i < nA; i += NT) sm.lc[i] = sm.l2c[i] / sumL;
-      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;
-    }
-    __syncthreads();
   }
-  if (ckpt && p.ckpt_every > 0 && p.iters % p.ckpt_every == 0)
-    write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS);
+  // Eqs. (15), (14) of the last pass
+  {
+    const float sumL = block_read<NT>(sm.redf[3]), sumR = block_read<NT>(sm.redf[2]);
+    if (ckpt && p.ckpt_every > 0 && p.iters % p.ckpt_every == 0)
+      write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS, sumL, sumR);
+    for (int i = t; i < nA; i += NT) sm.lc[i] = sm.lraw[i] / sumL;
+    for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;
+  }
+  __syncthreads();
 }
 
 // LDS budget of the one-image solver: most of a CU's 160 KB.
