@@ -749,41 +749,42 @@ struct HistTileSplit {
     const int64_t K = lag + ngrad;                      // iterations (covers nload)
     int64_t k = 0;
     if (d.in_vec && N >= PX) {
-      const int64_t nfull = (E - P0) / STEP;  // load steps whose chunks are all full
-      uint32_t buf[PREFETCH][NW];
+      // The halves run loops of their own, one barrier per iteration each
+      // (K in both), so the producer's loads sit outside any branch and the
+      // compiler waits only for the oldest step in flight.  `producer` is
+      // uniform per wave (NH is a multiple of 64).
       if (producer) {
+        const int64_t nfull = (E - P0) / STEP;  // load steps whose chunks are all full
+        uint32_t buf[PREFETCH][NW];
 #pragma unroll
         for (int j = 0; j < PREFETCH; ++j) load_words<NW, false>(chunk_or_first(P0 + (int64_t)j * STEP), buf[j]);
-      }
-      while (k + PREFETCH <= nfull) {
+        while (k + PREFETCH <= nfull) {
 #pragma unroll
-        for (int kk = 0; kk < PREFETCH; ++kk) {
-          if (producer) {
+          for (int kk = 0; kk < PREFETCH; ++kk) {
             load_step(P0 + k * STEP, buf[kk], true);
             load_words<NW, false>(chunk_or_first(P0 + (k + PREFETCH) * STEP), buf[kk]);
-          } else if (k >= lag) {
-            grad_step(P0 + (k - lag) * STEP);
+            bare_barrier();
+            ++k;
           }
-          bare_barrier();
-          ++k;
         }
-      }
-      while (k < K) {
+        while (k < K) {
 #pragma unroll
-        for (int kk = 0; kk < PREFETCH; ++kk) {
-          if (k < K) {  // uniform
-            if (producer) {
+          for (int kk = 0; kk < PREFETCH; ++kk) {
+            if (k < K) {  // uniform
               if (k < nload) {
                 const int64_t p = P0 + k * STEP + (int64_t)tt * PX;
                 load_step(P0 + k * STEP, buf[kk], p + PX <= E);
               }
               load_words<NW, false>(chunk_or_first(P0 + (k + PREFETCH) * STEP), buf[kk]);
-            } else if (k >= lag) {
-              grad_step(P0 + (k - lag) * STEP);
+              bare_barrier();
+              ++k;
             }
-            bare_barrier();
-            ++k;
           }
+        }
+      } else {
+        for (; k < K; ++k) {
+          if (k >= lag) grad_step(P0 + (k - lag) * STEP);
+          bare_barrier();
         }
       }
     } else {
@@ -1175,12 +1176,38 @@ __device__ inline void wave_partial(float x, float* red) {
   if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = x;
 }
 
+// Block sums of the wave partials in ra and rb (NT / 64 <= 16 entries each),
+// in every lane: one LDS read per wave (row 0 of the wave takes ra, row 1
+// takes rb), a scan inside the rows, then lanes 15 and 31.  Every wave adds
+// in the same order, so all lanes get the same bits.
+template <int NT>
+__device__ inline float2 block_read2(const float* ra, const float* rb) {
+  constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "one row of lanes per array");
+  const int lane = threadIdx.x & 63;
+  float x = 0.f;
+  if (lane < NW)
+    x = ra[lane];
+  else if (lane >= 16 && lane < 16 + NW)
+    x = rb[lane - 16];
+  x += dpp_get<dpp::ROW_SHR + 1, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 2, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 4, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 8, 0xf>(x);
+  return make_float2(read_lane(x, 15), read_lane(x, 31));
+}
+
 template <int NT>
 __device__ inline float block_read(const float* red) {
-  float s = red[0];
-#pragma unroll
-  for (int i = 1; i < NT / 64; ++i) s += red[i];
-  return s;
+  constexpr int NW = NT / 64;
+  static_assert(NW <= 16, "one row of lanes");
+  const int lane = threadIdx.x & 63;
+  float x = lane < NW ? red[lane] : 0.f;
+  x += dpp_get<dpp::ROW_SHR + 1, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 2, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 4, 0xf>(x);
+  x += dpp_get<dpp::ROW_SHR + 8, 0xf>(x);
+  return read_lane(x, 15);
 }
 
 // largest power of two <= x (x >= 1), capped at 64
@@ -1472,11 +1499,30 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     sm.rc[nB] = 0.f;
   }
   const ClassLanes cl = LIST ? ClassLanes{-1, 0, 1} : class_lanes<NT>(nA, t);
+  // class list: per round, the first lane of this lane's class in the wave
+  // (64: padding chunk) and the class this lane completes (-1: none)
+  constexpr int RMAX = SolveCore<BINS, NT>::RMAX;
+  int seg0r[RMAX], donecls[RMAX];
+  const int nchunks = LIST ? sm.off[BINS] : 0;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    seg0r[r] = 64;
+    donecls[r] = -1;
+    if (LIST && r < R) {
+      const int u = r * NT + t;
+      const int cls = sm.chunk_cls[u];
+      if (cls >= 0) {
+        seg0r[r] = sm.off[cls] & 63;
+        if ((u - sm.off[cls] + 1) * C >= sm.csz[cls]) donecls[r] = cls;
+      }
+    }
+  }
   __syncthreads();
 
   for (int it = 0; it < p.iters; ++it) {
     // sums of the previous pass's L', R' (Eqs. 14, 15)
-    const float sumL = block_read<NT>(sm.redf[3]), sumR = block_read<NT>(sm.redf[2]);
+    const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
+    const float sumL = sums.x, sumR = sums.y;
     if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0)
       write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS, sumL, sumR);
     // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m, from the
@@ -1485,7 +1531,9 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
       const float sLR = sumL * sumR;
       if constexpr (LIST) {
         // one chunk per lane and round; a class is summed inside its wave
-        for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (r >= R || r * NT + (t & ~63) >= nchunks) break;  // whole wave of padding
           const int u = r * NT + t;
           const cell_t* cp = cells + (size_t)u * CS;
           // four independent partial sums (one per cell position mod 4) keep
@@ -1505,8 +1553,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
             for (int x = 0; x < 4; ++x) a4[x] = fmaf(sm.lraw[e[x] & MASK], sm.rn[e[x] >> SH], a4[x]);
           }
           float acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-          const int cls = sm.chunk_cls[u];
-          const int seg0 = cls >= 0 ? (sm.off[cls] & 63) : 64;  // lane of the class's first chunk
+          const int seg0 = seg0r[r];  // lane of the class's first chunk
           {  // inclusive segmented scan over the class's lanes
             float y;
             y = dpp_get<dpp::ROW_SHR + 1, 0xf>(acc);
@@ -1522,8 +1569,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
             y = dpp_get<dpp::BCAST31, 0xc>(acc);  // rows 2, 3 from lane 31
             if (31 >= seg0) acc += y;
           }
-          if (cls >= 0 && (u - sm.off[cls] + 1) * C >= sm.csz[cls])
-            sm.rho[cls] = acc > 0.f ? sm.sd[cls] * sLR / acc : 0.f;
+          if (donecls[r] >= 0) sm.rho[donecls[r]] = acc > 0.f ? sm.sd[donecls[r]] * sLR / acc : 0.f;
         }
       } else {
         // rows of A, each contributing a run of B, summed as a difference of
@@ -1577,6 +1623,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
       const float denR = block_read<NT>(sm.redf[0]) + p.beta;
       float qr = 0.f, sr = 0.f;
       for (int base = 0; base < nB * Gc; base += NT) {
+        if (base + (t & ~63) >= nB * Gc) break;  // whole wave past the outputs
         const int q = base + t;
         const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
         const int s0 = k * Lc;  // a multiple of 4
@@ -1626,6 +1673,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
       const float denL = block_read<NT>(sm.redf[1]) + p.alpha;
       float sl = 0.f;
       for (int base = 0; base < nA * Gr; base += NT) {
+        if (base + (t & ~63) >= nA * Gr) break;  // whole wave past the outputs
         const int q = base + t;
         const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
         const int s0 = k * Lr;
