@@ -171,30 +171,39 @@ __device__ inline int image_of_item(const ImgDesc* desc, int n, int it) {
 }
 
 template <int BITS>
-__global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgDesc* desc, ImageState* st,
-                                                    uint32_t* lists_base, int64_t lists_stride, uint32_t* flags) {
+__global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgDesc* __restrict__ desc,
+                                                    ImageState* st, uint32_t* lists_base, int64_t lists_stride,
+                                                    uint32_t* flags) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ BatchSmem<BITS> sm;
   __shared__ uint32_t red[NT_BATCH / 64];
   __shared__ int item_s;
   __shared__ uint32_t last_s;
   const int64_t st_words = ImageState::words(BINS);
-  int tab_img = -1;  // image whose remap table is in LDS
+  // fixed for the launch (only `next` changes on the device)
+  const int ht = hdr->total_tiles, nitems = ht + hdr->total_rtiles, nimg = hdr->n;
+  const int64_t tile_px = hdr->tile_px, rtile_px = hdr->rtile_px;
+  int tab_img = -1;    // image whose remap table is in LDS
+  int claimed = -1;    // item claimed ahead by thread 0
   for (;;) {
-    if (threadIdx.x == 0) item_s = (int)atomicAdd(&hdr->next, 1u);
+    if (threadIdx.x == 0) item_s = claimed >= 0 ? claimed : (int)atomicAdd(&hdr->next, 1u);
     __syncthreads();
-    const int item = item_s;
+    const int item = __builtin_amdgcn_readfirstlane(item_s);
     __syncthreads();
-    const int ht = hdr->total_tiles;
-    if (item >= ht + hdr->total_rtiles) break;
+    if (item >= nitems) break;
     const bool is_hist = item < ht;
+    // Items are claimed in increasing order, so the item after a remap item
+    // is a remap item too, and remap items never run the solver: claim it
+    // now and let the atomic's round trip overlap this item.  After a
+    // histogram item this workgroup may run the solver, and an item held
+    // meanwhile would wait for it, so that claim waits for the loop's top.
+    if (threadIdx.x == 0) claimed = is_hist ? -1 : (int)atomicAdd(&hdr->next, 1u);
     const int tile = is_hist ? item : item - ht;
-    const int i = is_hist ? image_of_item<false>(desc, hdr->n, tile) : image_of_item<true>(desc, hdr->n, tile);
+    const int i = is_hist ? image_of_item<false>(desc, nimg, tile) : image_of_item<true>(desc, nimg, tile);
     ImageState* s = reinterpret_cast<ImageState*>(reinterpret_cast<uint32_t*>(st) + i * st_words);
     {
       const ImgDesc d = desc[i];
       if (is_hist) {
-        const int64_t tile_px = hdr->tile_px;
         const int local = tile - d.tile0;
         const int64_t P0 = (int64_t)local * tile_px;
         const int64_t P1 = min(P0 + tile_px, d.npix);
@@ -226,7 +235,6 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
           __syncthreads();
           tab_img = i;
         }
-        const int64_t rtile_px = hdr->rtile_px;
         const int64_t P0 = (int64_t)(tile - d.rtile0) * rtile_px;
         const int64_t P1 = min(P0 + rtile_px, d.npix);
         remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
