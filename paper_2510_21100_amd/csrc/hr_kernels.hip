@@ -103,19 +103,28 @@ __global__ void k_batch_reset(BatchHeader* hdr, ImageState* st, int bins) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
        i += (int64_t)gridDim.x * blockDim.x)
     base[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->next = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    hdr->next = 0;
+    hdr->rhead = 0;
+    hdr->nready = 0;
+  }
 }
 
+
+__device__ inline ImageState* state_of(ImageState* st, int64_t st_words, int i) {
+  return reinterpret_cast<ImageState*>(reinterpret_cast<uint32_t*>(st) + i * st_words);
+}
 
 // Completes image i once all its histogram items are merged: adds up the
 // partial histograms, rebins the gradient histogram, runs the solver and the
 // LUT, then publishes the LUT.  Everything it needs is re-read from the
 // tables, so nothing of the item loop stays live across the solver.
 template <int BITS>
-__device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageState* s, int i,
+__device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImageState* st, int64_t st_words, int i,
                              uint32_t* lists_base, int64_t lists_stride, uint32_t* flags, BatchSmem<BITS>& sm,
                              uint32_t* red) {
   constexpr int BINS = Cfg<BITS>::BINS;
+  ImageState* s = state_of(st, st_words, i);
   uint32_t* hs = s->hs();
   uint32_t* graw = s->graw(BINS);
   uint32_t* hg = s->hg(BINS);
@@ -155,19 +164,64 @@ __device__ void finish_image(const BatchHeader* hdr, const ImgDesc* desc, ImageS
   }
   drain_memory();
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(to_global(&s->ready), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(to_global(&s->ready), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // append to the ready list: position by arrival, entry = image + 1
+    const uint32_t pos = atomicAdd(&hdr->nready, 1u);
+    __hip_atomic_store(to_global(&state_of(st, st_words, (int)pos)->fifo), (uint32_t)i + 1u, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// image owning item `it` of a range [first[i], first[i] + count[i]) per image
-// (first ascending over the descriptor table)
-template <bool REMAP>
+// image owning histogram item `it` (tile0 ascending over the descriptor table)
 __device__ inline int image_of_item(const ImgDesc* desc, int n, int it) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if ((REMAP ? desc[mid].rtile0 : desc[mid].tile0) <= it) lo = mid; else hi = mid - 1;
+    if (desc[mid].tile0 <= it) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Claims a remap item (thread 0): the next tile of image `cur` if it has one,
+// else of the image at the head of the ready list, advancing the head past
+// images whose tiles are all claimed and waiting while the head's image is
+// not yet published.  img = -1 once every image is claimed out.  Every image
+// has at least one histogram item, so every position is published in the end.
+__device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImageState* st, int64_t st_words, int n,
+                                   int cur, int& img, int& tl) {
+  if (cur >= 0) {
+    const uint32_t t = atomicAdd(&state_of(st, st_words, cur)->rnext, 1u);
+    if (t < (uint32_t)desc[cur].rtiles) {
+      img = cur;
+      tl = (int)t;
+      return;
+    }
+  }
+  for (;;) {
+    const uint32_t pos = __hip_atomic_load(to_global(&hdr->rhead), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (pos >= (uint32_t)n) {
+      img = -1;
+      tl = -1;
+      return;
+    }
+    const uint32_t v = __hip_atomic_load(to_global(&state_of(st, st_words, (int)pos)->fifo), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    if (v == 0u) {  // published position not written yet
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    const int c = (int)v - 1;
+    const uint32_t t = atomicAdd(&state_of(st, st_words, c)->rnext, 1u);
+    if (t < (uint32_t)desc[c].rtiles) {
+      img = c;
+      tl = (int)t;
+      return;
+    }
+    uint32_t expect = pos;
+    __hip_atomic_compare_exchange_strong(to_global(&hdr->rhead), &expect, pos + 1u, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <int BITS>
@@ -180,72 +234,76 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
   __shared__ int item_s;
   __shared__ uint32_t last_s;
   const int64_t st_words = ImageState::words(BINS);
-  // fixed for the launch (only `next` changes on the device)
-  const int ht = hdr->total_tiles, nitems = ht + hdr->total_rtiles, nimg = hdr->n;
+  // fixed for the launch (the queue cursors change on the device)
+  const int ht = hdr->total_tiles, nimg = hdr->n;
   const int64_t tile_px = hdr->tile_px, rtile_px = hdr->rtile_px;
-  int tab_img = -1;    // image whose remap table is in LDS
-  int claimed = -1;    // item claimed ahead by thread 0
+  int tab_img = -1;  // image whose remap table is in LDS
+  // Histogram items, in queue order.  The workgroup that merges an image's
+  // last item runs its solver and publishes it in the ready list.
   for (;;) {
-    if (threadIdx.x == 0) item_s = claimed >= 0 ? claimed : (int)atomicAdd(&hdr->next, 1u);
+    if (threadIdx.x == 0) item_s = (int)atomicAdd(&hdr->next, 1u);
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(item_s);
     __syncthreads();
-    if (item >= nitems) break;
-    const bool is_hist = item < ht;
-    // Items are claimed in increasing order, so the item after a remap item
-    // is a remap item too, and remap items never run the solver: claim it
-    // now and let the atomic's round trip overlap this item.  After a
-    // histogram item this workgroup may run the solver, and an item held
-    // meanwhile would wait for it, so that claim waits for the loop's top.
-    if (threadIdx.x == 0) claimed = is_hist ? -1 : (int)atomicAdd(&hdr->next, 1u);
-    const int tile = is_hist ? item : item - ht;
-    const int i = is_hist ? image_of_item<false>(desc, nimg, tile) : image_of_item<true>(desc, nimg, tile);
-    ImageState* s = reinterpret_cast<ImageState*>(reinterpret_cast<uint32_t*>(st) + i * st_words);
-    {
-      const ImgDesc d = desc[i];
-      if (is_hist) {
-        const int local = tile - d.tile0;
-        const int64_t P0 = (int64_t)local * tile_px;
-        const int64_t P1 = min(P0 + tile_px, d.npix);
-        uint32_t* part = s->slot(BINS, local % ImageState::NSLOT);
-        hist_tile<BITS, NT_BATCH>(d, P0, P1, sm.hist, part, part + BINS);
-        tab_img = -1;
-        if (threadIdx.x == 0) {
-          if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
-          fence_release_agent();
-          const bool last = atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1;
-          if (last) fence_acquire_agent();
-          last_s = last ? 1u : 0u;
-        }
-      } else {
-        if (tab_img != i) {
-          if (threadIdx.x == 0) {
-            while (__hip_atomic_load(to_global(&s->ready), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-              __builtin_amdgcn_s_sleep(2);
-            fence_acquire_agent();
-          }
-          __syncthreads();
-          const uint16_t* lut = s->lut(BINS);
-          for (int v = threadIdx.x; v < BINS; v += NT_BATCH) {
-            const uint32_t L = __hip_atomic_load(to_global(reinterpret_cast<const uint32_t*>(lut)) + (v >> 1),
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
-            sm.tab[v] = remap_entry((uint32_t)v, lv);
-          }
-          __syncthreads();
-          tab_img = i;
-        }
-        const int64_t P0 = (int64_t)(tile - d.rtile0) * rtile_px;
-        const int64_t P1 = min(P0 + rtile_px, d.npix);
-        remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
-        if (threadIdx.x == 0) last_s = 0;
+    if (item >= ht) break;
+    const int i = image_of_item(desc, nimg, item);
+    ImageState* s = state_of(st, st_words, i);
+    const ImgDesc d = desc[i];
+    const int local = item - d.tile0;
+    const int64_t P0 = (int64_t)local * tile_px;
+    const int64_t P1 = min(P0 + tile_px, d.npix);
+    uint32_t* part = s->slot(BINS, local % ImageState::NSLOT);
+    hist_tile<BITS, NT_BATCH>(d, P0, P1, sm.hist, part, part + BINS);
+    if (threadIdx.x == 0) {
+      if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
+      fence_release_agent();
+      const bool last = atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1;
+      if (last) fence_acquire_agent();
+      last_s = last ? 1u : 0u;
+    }
+    __syncthreads();
+    if (last_s) finish_image<BITS>(hdr, desc, st, st_words, i, lists_base, lists_stride, flags, sm, red);
+    __syncthreads();
+  }
+  // Remap items, images in the order their LUTs were published, so that no
+  // workgroup waits on a solve while a published image has items left.
+  // Thread 0 claims the next item of the same image while this one runs.
+  int cur = -1, ahead = -1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int img = cur, tl = ahead;
+      if (tl < 0) claim_remap(hdr, desc, st, st_words, nimg, cur, img, tl);
+      item_s = img;
+      last_s = (uint32_t)tl;
+      cur = img;
+      ahead = -1;
+      if (img >= 0) {
+        const uint32_t t2 = atomicAdd(&state_of(st, st_words, img)->rnext, 1u);
+        if (t2 < (uint32_t)desc[img].rtiles) ahead = (int)t2;
       }
     }
     __syncthreads();
-    if (last_s) {
-      finish_image<BITS>(hdr, desc, s, i, lists_base, lists_stride, flags, sm, red);
-      tab_img = -1;
+    const int i = __builtin_amdgcn_readfirstlane(item_s);
+    const int tile = __builtin_amdgcn_readfirstlane((int)last_s);
+    __syncthreads();
+    if (i < 0) break;
+    const ImgDesc d = desc[i];
+    if (tab_img != i) {
+      if (threadIdx.x == 0) fence_acquire_agent();  // pairs with the ready list's release
+      __syncthreads();
+      const uint16_t* lut = state_of(st, st_words, i)->lut(BINS);
+      for (int v = threadIdx.x; v < BINS; v += NT_BATCH) {
+        const uint32_t L = __hip_atomic_load(to_global(reinterpret_cast<const uint32_t*>(lut)) + (v >> 1),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
+        sm.tab[v] = remap_entry((uint32_t)v, lv);
+      }
+      __syncthreads();
+      tab_img = i;
     }
+    const int64_t P0 = (int64_t)tile * rtile_px;
+    const int64_t P1 = min(P0 + rtile_px, d.npix);
+    remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
     __syncthreads();
   }
 }

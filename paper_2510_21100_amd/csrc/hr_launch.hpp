@@ -47,12 +47,12 @@ struct BatchOut {
 // Header of the batched descriptor table (device copy written per call, so a
 // captured launch graph serves every call).
 struct BatchHeader {
-  uint32_t next;         // work-queue cursor (reset on the device each call)
-  uint32_t pad0;
+  uint32_t next;         // histogram-item cursor (reset on the device each call)
+  uint32_t rhead;        // ready-list position being remapped (reset each call)
   int32_t n;             // images in this call
   int32_t total_tiles;   // histogram items over all images
   int32_t total_rtiles;  // remap items over all images
-  int32_t pad1;
+  uint32_t nready;       // images in the ready list (reset each call)
   int64_t tile_px;       // pixels per histogram item (multiple of the pixel step)
   int64_t rtile_px;      // pixels per remap item (multiple of the pixel step)
   SolveParams params;
@@ -67,7 +67,8 @@ struct ImageState {
   static constexpr int NSLOT = 8;
   uint32_t done;   // histogram items merged so far
   uint32_t ready;  // LUT published
-  uint32_t pad[2];
+  uint32_t fifo;   // ready list, position = this image's index: published image + 1 (0: not yet)
+  uint32_t rnext;  // remap tiles of this image claimed so far
   static constexpr int64_t words(int bins) { return 4 + 5 * (int64_t)bins + bins / 2 + NSLOT * 3LL * bins; }
   __host__ __device__ uint32_t* base() { return reinterpret_cast<uint32_t*>(this); }
   __host__ __device__ uint32_t* hs() { return base() + 4; }
