@@ -1448,6 +1448,68 @@ __device__ inline ClassLanes class_lanes(int nA, int t) {
   return r;
 }
 
+// Cell words of a class-list chunk, four at a time.
+template <typename cell_t>
+__device__ __forceinline__ void cells_of(const cell_t* q, uint32_t* e) {
+  if constexpr (sizeof(cell_t) == 2) {
+    const v2u w = *reinterpret_cast<const v2u*>(q);
+    e[0] = w.x & 0xffffu;
+    e[1] = w.x >> 16;
+    e[2] = w.y & 0xffffu;
+    e[3] = w.y >> 16;
+  } else {
+    const v4u w = *reinterpret_cast<const v4u*>(q);
+    e[0] = w.x;
+    e[1] = w.y;
+    e[2] = w.z;
+    e[3] = w.w;
+  }
+}
+
+// sum over s in [s0, s1) of x[s] rho[class], classes one byte each from the
+// table row (4 per word, zero past np); s0 and s1 - s0 multiples of 4, x
+// zero-padded.  Four partial sums (s mod 4) in fixed order; eight cells at a
+// time with all gathers issued before the first product.
+__device__ __forceinline__ float table_dot(const float* x, const uint32_t* trow, const float* rho, int s0, int s1,
+                                           int np) {
+  float a4[4] = {0.f, 0.f, 0.f, 0.f};
+  int s = s0;
+  for (; s + 8 <= s1; s += 8) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const v4u x1 = *reinterpret_cast<const v4u*>(x + s + 4);
+    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
+    const uint32_t c1 = s + 4 < np ? trow[(s >> 2) + 1] : 0u;
+    float r[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = rho[(c0 >> (8 * q)) & 0xffu];
+      r[4 + q] = rho[(c1 >> (8 * q)) & 0xffu];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+    a4[0] = fmaf(__uint_as_float(x1.x), r[4], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x1.y), r[5], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x1.z), r[6], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x1.w), r[7], a4[3]);
+  }
+  if (s < s1) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
+    float r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = rho[(c0 >> (8 * q)) & 0xffu];
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+  }
+  return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+}
+
 // Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
 // the values the next pass works with.
 template <int BINS, int NT>
@@ -1536,21 +1598,36 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           if (r >= R || r * NT + (t & ~63) >= nchunks) break;  // whole wave of padding
           const int u = r * NT + t;
           const cell_t* cp = cells + (size_t)u * CS;
-          // four independent partial sums (one per cell position mod 4) keep
-          // several gathers in flight; fixed order, so deterministic
+          // four partial sums (cell position mod 4), fixed order; eight cells
+          // at a time, all sixteen gathers issued before the first product
           float a4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-          for (int k = 0; k < C; k += 4) {
-            uint32_t e[4];
-            if constexpr (sizeof(cell_t) == 2) {
-              const v2u w = *reinterpret_cast<const v2u*>(cp + k);
-              e[0] = w.x & 0xffffu; e[1] = w.x >> 16; e[2] = w.y & 0xffffu; e[3] = w.y >> 16;
-            } else {
-              const v4u w = *reinterpret_cast<const v4u*>(cp + k);
-              e[0] = w.x; e[1] = w.y; e[2] = w.z; e[3] = w.w;
-            }
+          int k = 0;
+          for (; k + 8 <= C; k += 8) {
+            uint32_t e[8];
+            cells_of<cell_t>(cp + k, e);
+            cells_of<cell_t>(cp + k + 4, e + 4);
+            float lv[8], rv[8];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) a4[x] = fmaf(sm.lraw[e[x] & MASK], sm.rn[e[x] >> SH], a4[x]);
+            for (int x = 0; x < 8; ++x) {
+              lv[x] = sm.lraw[e[x] & MASK];
+              rv[x] = sm.rn[e[x] >> SH];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 0; x < 8; ++x) a4[x & 3] = fmaf(lv[x], rv[x], a4[x & 3]);
+          }
+          if (k < C) {  // C is a multiple of 4
+            uint32_t e[4];
+            cells_of<cell_t>(cp + k, e);
+            float lv[4], rv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              lv[x] = sm.lraw[e[x] & MASK];
+              rv[x] = sm.rn[e[x] >> SH];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a4[x] = fmaf(lv[x], rv[x], a4[x]);
           }
           float acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
           const int seg0 = seg0r[r];  // lane of the class's first chunk
@@ -1630,17 +1707,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
-          float a4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-          for (int s = s0; s < s0 + Lc; s += 4) {
-            const v4u xv = *reinterpret_cast<const v4u*>(&sm.l2c[s]);
-            const uint32_t cls4 = s < nAp ? trow[s >> 2] : 0u;
-            a4[0] = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], a4[0]);
-            a4[1] = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], a4[1]);
-            a4[2] = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], a4[2]);
-            a4[3] = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], a4[3]);
-          }
-          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          acc = table_dot(sm.l2c, trow, sm.rho, s0, s0 + Lc, nAp);
         } else {
           const int b = sm.B[o];
           float a4[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1680,17 +1747,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
-          float a4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-          for (int s = s0; s < s0 + Lr; s += 4) {
-            const v4u xv = *reinterpret_cast<const v4u*>(&sm.wc[s]);
-            const uint32_t cls4 = s < nBp ? trow[s >> 2] : 0u;
-            a4[0] = fmaf(__uint_as_float(xv.x), sm.rho[cls4 & 0xff], a4[0]);
-            a4[1] = fmaf(__uint_as_float(xv.y), sm.rho[(cls4 >> 8) & 0xff], a4[1]);
-            a4[2] = fmaf(__uint_as_float(xv.z), sm.rho[(cls4 >> 16) & 0xff], a4[2]);
-            a4[3] = fmaf(__uint_as_float(xv.w), sm.rho[cls4 >> 24], a4[3]);
-          }
-          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          acc = table_dot(sm.wc, trow, sm.rho, s0, s0 + Lr, nBp);
         } else {
           const int a = sm.A[o];
           float a4[4] = {0.f, 0.f, 0.f, 0.f};
