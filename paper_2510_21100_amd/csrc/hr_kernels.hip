@@ -183,21 +183,13 @@ __device__ inline int image_of_item(const ImgDesc* desc, int n, int it) {
   return lo;
 }
 
-// Claims a remap item (thread 0): the next tile of image `cur` if it has one,
-// else of the image at the head of the ready list, advancing the head past
-// images whose tiles are all claimed and waiting while the head's image is
-// not yet published.  img = -1 once every image is claimed out.  Every image
-// has at least one histogram item, so every position is published in the end.
+// Claims a remap item (thread 0) from the image at the head of the ready
+// list, advancing the head past images whose tiles are all claimed and
+// waiting while the head's position is not yet written.  img = -1 once every
+// image is claimed out.  Every image has at least one histogram item, so every
+// position of the list is written in the end.
 __device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImageState* st, int64_t st_words, int n,
-                                   int cur, int& img, int& tl) {
-  if (cur >= 0) {
-    const uint32_t t = atomicAdd(&state_of(st, st_words, cur)->rnext, 1u);
-    if (t < (uint32_t)desc[cur].rtiles) {
-      img = cur;
-      tl = (int)t;
-      return;
-    }
-  }
+                                   int& img, int& tl) {
   for (;;) {
     const uint32_t pos = __hip_atomic_load(to_global(&hdr->rhead), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (pos >= (uint32_t)n) {
@@ -267,25 +259,29 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
   }
   // Remap items, images in the order their LUTs were published, so that no
   // workgroup waits on a solve while a published image has items left.
-  // Thread 0 claims the next item of the same image while this one runs.
-  int cur = -1, ahead = -1;
+  // Thread 0 claims the next tile of the same image while this one runs; the
+  // barriers here order LDS only (lds_wait + s_barrier), so the claim's
+  // atomic stays in flight until the next item starts.
+  int cur = -1;
+  uint32_t ahead = 0xffffffffu;  // thread 0: tile claimed ahead on image cur
   for (;;) {
     if (threadIdx.x == 0) {
-      int img = cur, tl = ahead;
-      if (tl < 0) claim_remap(hdr, desc, st, st_words, nimg, cur, img, tl);
+      int img = -1, tl = -1;
+      if (cur >= 0 && ahead < (uint32_t)desc[cur].rtiles) {
+        img = cur;
+        tl = (int)ahead;
+      } else {
+        claim_remap(hdr, desc, st, st_words, nimg, img, tl);
+      }
       item_s = img;
       last_s = (uint32_t)tl;
       cur = img;
-      ahead = -1;
-      if (img >= 0) {
-        const uint32_t t2 = atomicAdd(&state_of(st, st_words, img)->rnext, 1u);
-        if (t2 < (uint32_t)desc[img].rtiles) ahead = (int)t2;
-      }
+      ahead = img >= 0 ? atomicAdd(&state_of(st, st_words, img)->rnext, 1u) : 0xffffffffu;
     }
-    __syncthreads();
+    lds_wait();
+    bare_barrier();
     const int i = __builtin_amdgcn_readfirstlane(item_s);
     const int tile = __builtin_amdgcn_readfirstlane((int)last_s);
-    __syncthreads();
     if (i < 0) break;
     const ImgDesc d = desc[i];
     if (tab_img != i) {
@@ -298,13 +294,15 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
         const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
         sm.tab[v] = remap_entry((uint32_t)v, lv);
       }
-      __syncthreads();
+      lds_wait();
+      bare_barrier();
       tab_img = i;
     }
     const int64_t P0 = (int64_t)tile * rtile_px;
     const int64_t P1 = min(P0 + rtile_px, d.npix);
     remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
-    __syncthreads();
+    lds_wait();  // every wave is done with item_s and the table before they change
+    bare_barrier();
   }
 }
 
