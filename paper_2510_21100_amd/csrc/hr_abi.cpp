@@ -35,7 +35,7 @@ constexpr int kPlainTileSteps = 16;  // upper bound; small images take fewer
 constexpr int kPlainWgPerCu = 4;     // one-image kernels aim for this many tiles per CU
 constexpr int kDefaultTileSteps = 32;
 constexpr int kDefaultWgPerCu = 1;
-constexpr int kDefaultRemapSteps = 16;
+constexpr int kDefaultRemapSteps = 8;
 constexpr int kStaging = 2;
 
 // pixels per workgroup of the one-image kernels: at most kPlainTileSteps

@@ -17,9 +17,9 @@ import math
 import os
 from typing import Sequence
 
-TILE_STEPS = (8, 16, 32, 64, 128)
+TILE_STEPS = (8, 16, 24, 32, 48, 64, 128)
 WG_PER_CU = (1,)
-REMAP_STEPS = (2, 4, 8, 16, 32)
+REMAP_STEPS = (4, 8, 16, 24, 32, 48, 64)
 
 
 def key(bins: int, esz: int, npix: int, n: int) -> str:
