@@ -29,7 +29,7 @@
 namespace hr {
 
 constexpr int DIFF_BINS = 256;
-constexpr int NT_VJP = 256;   // one thread per level in the reverse pass
+constexpr int NT_VJP = 1024;  // reverse pass: outputs split over lane groups, classes over balanced lanes
 constexpr int SEG_MAX = 16;   // largest checkpoint interval
 constexpr double G_SCALE = 16777216.0;       // 2^24: fixed point of G[v]
 constexpr double LOSS_SCALE = 4294967296.0;  // 2^32: fixed point of the squared errors
@@ -235,54 +235,81 @@ struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   float rhb[DIFF_BINS];                              // adjoint of rho, then of d
   float gH[DIFF_BINS];                               // dLoss/dh~ (dense)
   double theta[DIFF_BINS];                           // Eq. (17) on A
+  double qc1[DIFF_BINS + 1], qc2[DIFF_BINS + 1];     // running sums over B (class sums)
+  double part[NT_VJP];                               // lane partials of the class sums
   float redv[NT_VJP / 64];
   double redd[NT_VJP / 64];
   float sc_Q, sc_P, sc_Sl, sc_Sr;
 };
 
-// out[j] = sum_i x[i] * tab[class(A_i, B_j)] for j < nB (one thread per j)
+// out[o] = sum_k x[k] * tab[cls(o, k)] for o < nout, k < nin: G lanes per
+// output (a power of two), lane k of the group taking a contiguous slice of
+// the inputs, summed in fixed order (slice, then the group's DPP sum).
 template <typename ClassFn>
-__device__ inline void col_gather(const VjpSmem& sm, const float* x, const float* tab, float* out, ClassFn cls) {
-  const int j = threadIdx.x;
-  if (j < sm.nB) {
+__device__ inline void lane_gather(int nout, int nin, const float* x, const float* tab, float* out, ClassFn cls) {
+  const int t = threadIdx.x;
+  const int G = nout <= NT_VJP ? pow2_floor64(NT_VJP / max(nout, 1)) : 1;
+  const int L = (nin + G - 1) / G;
+  for (int base = 0; base < nout * G; base += NT_VJP) {
+    if (base + (t & ~63) >= nout * G) break;  // whole wave past the outputs
+    const int q = base + t;
+    const int o = min(q / G, nout - 1), k = q & (G - 1);
+    const int k0 = k * L, k1 = min(k0 + L, nin);
     float a4[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int i = 0; i < sm.nA; ++i) a4[i & 3] = fmaf(x[i], tab[cls(i, j)], a4[i & 3]);
-    out[j] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    for (int kk = k0; kk < k1; ++kk) a4[(kk - k0) & 3] = fmaf(x[kk], tab[cls(o, kk)], a4[(kk - k0) & 3]);
+    float acc = group_sum_last((a4[0] + a4[1]) + (a4[2] + a4[3]), G);
+    if (k == G - 1 && q / G < nout) out[o] = acc;
   }
 }
 
-// out[i] = sum_j y[j] * tab[class(A_i, B_j)] for i < nA (one thread per i)
+// out[j] = sum_i x[i] * tab[class(A_i, B_j)] for j < nB
+template <typename ClassFn>
+__device__ inline void col_gather(const VjpSmem& sm, const float* x, const float* tab, float* out, ClassFn cls) {
+  lane_gather(sm.nB, sm.nA, x, tab, out, [&](int j, int i) { return cls(i, j); });
+}
+
+// out[i] = sum_j y[j] * tab[class(A_i, B_j)] for i < nA
 template <typename ClassFn>
 __device__ inline void row_gather(const VjpSmem& sm, const float* y, const float* tab, float* out, ClassFn cls) {
-  const int i = threadIdx.x;
-  if (i < sm.nA) {
-    float a4[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < sm.nB; ++j) a4[j & 3] = fmaf(y[j], tab[cls(i, j)], a4[j & 3]);
-    out[i] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
-  }
+  lane_gather(sm.nA, sm.nB, y, tab, out, [&](int i, int j) { return cls(i, j); });
 }
 
 // out[m] = sum over the cells (i, j) of class m of p1[i] q1[j] + p2[i] q2[j]
-// (the second term only with TWO); classes with s_m = 0 get 0.
+// (the second term only with TWO); classes with s_m = 0 get 0.  Rows of a
+// class contribute runs of B, summed as differences of FP64 running sums of
+// q1, q2; the (class, row) pairs are spread over balanced lanes (class q
+// takes rows q..nA-1) and each class adds its lanes' partials in order.
 template <bool TWO>
-__device__ inline void class_sums(const VjpSmem& sm, const float* p1, const float* q1, const float* p2,
-                                  const float* q2, float* out) {
-  const int m = threadIdx.x;
-  float acc = 0.f;
-  if (sm.sd[m] > 0.f) {
-    for (int i = sm.PA[m]; i < sm.nA; ++i) {
+__device__ inline void class_sums(VjpSmem& sm, const ClassLanes& cl, const float* p1, const float* q1,
+                                  const float* p2, const float* q2, float* out) {
+  const int t = threadIdx.x;
+  const int nA = sm.nA, nB = sm.nB;
+  for (int j = t; j <= nB; j += NT_VJP) {
+    sm.qc1[j] = j < nB ? (double)q1[j] : 0.0;
+    if (TWO) sm.qc2[j] = j < nB ? (double)q2[j] : 0.0;
+  }
+  for (int m = t; m < DIFF_BINS; m += NT_VJP) out[m] = 0.f;
+  __syncthreads();
+  block_scan<NT_VJP, double>(sm.qc1, nB + 1, sm.redd);
+  if (TWO) block_scan<NT_VJP, double>(sm.qc2, nB + 1, sm.redd);
+  double acc = 0.0;
+  if (cl.q >= 0) {
+    const int m = sm.A[cl.q];
+    for (int i = cl.q + cl.k; i < nA; i += cl.g) {
       int jlo, jhi;
-      class_run<DIFF_BINS>(sm, i, m, jlo, jhi);
-      float a1 = 0.f, a2 = 0.f;
-      for (int j = jlo; j < jhi; ++j) {
-        a1 += q1[j];
-        if (TWO) a2 += q2[j];
-      }
-      acc = fmaf(p1[i], a1, acc);
-      if (TWO) acc = fmaf(p2[i], a2, acc);
+      class_run_upper<DIFF_BINS>(sm, i, m, jlo, jhi);  // empty: jlo = jhi
+      acc = fma((double)p1[i], sm.qc1[jhi] - sm.qc1[jlo], acc);
+      if (TWO) acc = fma((double)p2[i], sm.qc2[jhi] - sm.qc2[jlo], acc);
     }
   }
-  out[m] = acc;
+  sm.part[t] = acc;
+  __syncthreads();
+  if (cl.q >= 0 && cl.k == 0) {
+    double d = 0.0;
+    for (int x = 0; x < cl.g; ++x) d += sm.part[t + x];
+    out[sm.A[cl.q]] = (float)d;
+  }
+  __syncthreads();
 }
 
 struct IdxClass {
@@ -298,14 +325,13 @@ struct Idx1Class {
 
 // The quantities of one pass from the state (lt, rt): d, rho (Eq. 11),
 // u and R' (Eq. 13), v and L' (Eq. 12), and the sums Q, P, Sl, Sr.
-__device__ void vjp_forward_pass(VjpSmem& sm, const SolveParams& p) {
+__device__ void vjp_forward_pass(VjpSmem& sm, const ClassLanes& cl, const SolveParams& p) {
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
-  class_sums<false>(sm, sm.lt, sm.rt, nullptr, nullptr, sm.dcl);
+  class_sums<false>(sm, cl, sm.lt, sm.rt, nullptr, nullptr, sm.dcl);
   const float l2 = t < nA ? sm.lt[t] * sm.lt[t] : 0.f;
   if (t < nA) sm.l2[t] = l2;
-  __syncthreads();
-  sm.rh[t] = sm.dcl[t] > 0.f ? sm.sd[t] / sm.dcl[t] : 0.f;
+  if (t < DIFF_BINS) sm.rh[t] = sm.dcl[t] > 0.f ? sm.sd[t] / sm.dcl[t] : 0.f;
   const float Q = block_sum<NT_VJP>(l2, sm.redv);  // synchronises
   col_gather(sm, sm.l2, sm.rh, sm.u, IdxClass{sm});
   __syncthreads();
@@ -337,7 +363,8 @@ __device__ void vjp_forward_pass(VjpSmem& sm, const SolveParams& p) {
 // Reverse of one pass: (lb, rb) = adjoints of the normalised outputs on
 // entry, of the pass's input state (lt, rt) on exit.  Adds the pass's
 // contributions to dalpha, dbeta (every thread holds the same totals).
-__device__ void vjp_backward_pass(VjpSmem& sm, const SolveParams& p, double& dalpha, double& dbeta) {
+__device__ void vjp_backward_pass(VjpSmem& sm, const ClassLanes& cl, const SolveParams& p, double& dalpha,
+                                  double& dbeta) {
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
   const float Q = sm.sc_Q, P = sm.sc_P, Sl = sm.sc_Sl, Sr = sm.sc_Sr;
@@ -379,11 +406,10 @@ __device__ void vjp_backward_pass(VjpSmem& sm, const SolveParams& p, double& dal
   // u_b = sum_a L_a^2 rho(a,b): z_a = sum_b ubar_b rho(a,b)
   row_gather(sm, sm.ub, sm.rh, sm.ta, IdxClass{sm});
   // rho-bar_m = sum over class m of vbar_a R'_b R_b + L_a^2 ubar_b
-  class_sums<true>(sm, sm.vb, sm.w, sm.l2, sm.ub, sm.rhb);
-  __syncthreads();
+  class_sums<true>(sm, cl, sm.vb, sm.w, sm.l2, sm.ub, sm.rhb);
   if (t < nA) sm.lb[t] += 2.f * sm.lt[t] * sm.ta[t];
   // rho = s / d: d-bar = -rho-bar rho / d
-  sm.rhb[t] = sm.dcl[t] > 0.f ? -sm.rhb[t] * sm.rh[t] / sm.dcl[t] : 0.f;
+  if (t < DIFF_BINS) sm.rhb[t] = sm.dcl[t] > 0.f ? -sm.rhb[t] * sm.rh[t] / sm.dcl[t] : 0.f;
   __syncthreads();
   // d_m = sum over class m of L_a R_b
   row_gather(sm, sm.rt, sm.rhb, sm.ta, IdxClass{sm});
@@ -409,7 +435,8 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
     const int a = sm.A[t];
     sm.theta[t] = a ? pow((double)a / (double)(BINS - 1), p.inv_gamma) : 0.0;  // Eq. (17)
   }
-  sm.gH[t] = dtarget[(size_t)img * BINS + t];
+  if (t < BINS) sm.gH[t] = dtarget[(size_t)img * BINS + t];
+  const ClassLanes cl = class_lanes<NT_VJP>(nA, t);
   // final state
   const float* last = ck + (size_t)(ncp - 1) * 2 * BINS;
   if (t < nA) sm.lt[t] = last[sm.A[t]];
@@ -434,7 +461,7 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
       if (t < nA) sm.lt[t] = sm.segl[q - 1][t];
       if (t < nB) sm.rt[t] = sm.segr[q - 1][t];
       __syncthreads();
-      vjp_forward_pass(sm, p);
+      vjp_forward_pass(sm, cl, p);
       if (t < nA) sm.segl[q][t] = sm.lp[t] / sm.sc_Sl;
       if (t < nB) sm.segr[q][t] = sm.rp[t] / sm.sc_Sr;
       __syncthreads();
@@ -443,8 +470,8 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
       if (t < nA) sm.lt[t] = sm.segl[q][t];
       if (t < nB) sm.rt[t] = sm.segr[q][t];
       __syncthreads();
-      vjp_forward_pass(sm, p);
-      vjp_backward_pass(sm, p, da, db);
+      vjp_forward_pass(sm, cl, p);
+      vjp_backward_pass(sm, cl, p, da, db);
     }
   }
   if (t == 0) {
