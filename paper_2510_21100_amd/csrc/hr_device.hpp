@@ -384,9 +384,16 @@ struct HistSmem {
                  : pow2_at_least(MaxWidth<BITS>::value + 2 * Pix<BITS, NT>::STEP);
   using pix_t = typename Cfg<BITS>::pix_t;
   static constexpr int RING_BYTES = RING * (int)sizeof(pix_t);
+  // Small gradients (raw level < GSMALL) take most pixels of smooth images and
+  // lanes of one wave tend to hit the same level.  With 10-bit pixels the
+  // split kernel has only 4 copies, and these levels count into one copy per
+  // lane, hgs[level * 64 + lane] (measured faster there; slower with the 16
+  // copies of 8-bit pixels, where the address select costs more than it saves).
+  static constexpr int GSMALL = (NT >= 1024 && BITS == 10) ? 32 : 0;
   uint32_t hs[BINS * STRIDE];
   uint32_t hg[(2 * BINS - 1) * STRIDE];
-  uint32_t ring[RING_BYTES / 4 + 16];  // + 64-byte mirror of the start: no wrap on reads
+  uint32_t hgs[GSMALL > 0 ? GSMALL * 64 : 4];
+  alignas(16) uint32_t ring[RING_BYTES / 4 + 16];  // + 64-byte mirror of the start: no wrap on reads
   uint32_t clamped;
 };
 
@@ -651,15 +658,21 @@ struct HistTileSplit {
   const bool producer;
   uint32_t* hs;
   uint32_t* hg;
+  uint32_t* hgl;  // this lane's copy of the small gradient levels
   int x;
   uint32_t clamped = 0;
+  static constexpr uint32_t GSMALL = SM::GSMALL;
 
   __device__ HistTileSplit(const ImgDesc& d_, int64_t p0, int64_t p1, SM& sm_)
       : d(d_), sm(sm_), P0(p0), P1(p1), N(d_.npix), E(min(p1 + (int64_t)d_.W, d_.npix)), W(d_.W),
         tt(threadIdx.x & (NH - 1)), step_mod_w(STEP % d_.W), producer(threadIdx.x < NH),
-        hs(sm_.hs + (threadIdx.x & (REP - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))) {
+        hs(sm_.hs + (threadIdx.x & (REP - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))),
+        hgl(sm_.hgs + (threadIdx.x & 63)) {
     x = (int)((P0 + (int64_t)tt * PX) % W);
   }
+
+  // counter of raw gradient level g for this lane
+  __device__ uint32_t* gslot(uint32_t g) const { return g < GSMALL ? hgl + g * 64 : hg + g * SD; }
 
   __device__ const uint8_t* chunk_or_first(int64_t at) const {
     const int64_t p = at + (int64_t)tt * PX;
@@ -714,15 +727,15 @@ struct HistTileSplit {
         for (int i = 0; i < PX; ++i) {
           const uint32_t vv = lane_of<pix_t>(own, i);
           const uint32_t vr = (i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last;
-          atomicAdd(&hg[grad_l1(vr, vv, lane_of<pix_t>(dn, i)) * SD], 1u);
+          atomicAdd(gslot(grad_l1(vr, vv, lane_of<pix_t>(dn, i))), 1u);
         }
         const int e = W - 1 - x;
         if (e < PX) {
           const uint32_t ve = lane_dyn<pix_t>(own, e);
           const uint32_t vre = (e + 1 < PX) ? lane_dyn<pix_t>(own, e + 1) : right_last;
           const uint32_t vde = lane_dyn<pix_t>(dn, e);
-          atomicSub(&hg[grad_l1(vre, ve, vde) * SD], 1u);
-          atomicAdd(&hg[grad_l1(ve, ve, vde) * SD], 1u);
+          atomicSub(gslot(grad_l1(vre, ve, vde)), 1u);
+          atomicAdd(gslot(grad_l1(ve, ve, vde)), 1u);
         }
       } else {
         int xx = x;
@@ -732,7 +745,7 @@ struct HistTileSplit {
             const uint32_t vv = lane_of<pix_t>(own, i);
             const uint32_t vr = (xx + 1 < W) ? ((i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last) : vv;
             const uint32_t vd = (q + i + W < N) ? lane_of<pix_t>(dn, i) : vv;
-            atomicAdd(&hg[grad_l1(vr, vv, vd) * SD], 1u);
+            atomicAdd(gslot(grad_l1(vr, vv, vd)), 1u);
             if (++xx == W) xx = 0;
           }
         }
@@ -811,6 +824,7 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
   const int t = threadIdx.x;
   for (int i = t; i < BINS * SD; i += NT) sm.hs[i] = 0;
   for (int i = t; i < (2 * BINS - 1) * SD; i += NT) sm.hg[i] = 0;
+  for (int i = t; i < SM::GSMALL * 64; i += NT) sm.hgs[i] = 0;
   if (t == 0) sm.clamped = 0;
   __syncthreads();
   uint32_t clamped;
@@ -835,6 +849,8 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
     uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < REP; ++r) s += sm.hg[k * SD + r];
+    if (k < SM::GSMALL)
+      for (int l = 0; l < 64; ++l) s += sm.hgs[k * 64 + l];  // counts wrap mod 2^32: a copy may hold a -1
     if (s) __hip_atomic_fetch_add(to_global(g_graw) + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // every wave's merge atomics are performed before any thread of the
