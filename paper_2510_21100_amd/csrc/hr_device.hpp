@@ -1086,7 +1086,6 @@ template <> struct CellT<1024> {
 template <int BINS, int NT>
 struct SolveCore {
   static constexpr int RMAX = BINS == 256 ? 2 : 1;  // rounds of chunks per lane
-  static constexpr int KS = BINS == 256 ? 8 : 1;    // row slices per class in the build
   static constexpr int PAD = BINS + 256;            // zero padding of the sweep inputs (G * L <= 2n + 256)
   float sc[BINS], gc[BINS];                         // s, g on A, B
   float lc[BINS + 4], rc[BINS + 4];                 // current L on A, R on B; [n] = 0
@@ -1102,7 +1101,7 @@ struct SolveCore {
   int32_t off[BINS + 1];                            // first chunk of class m
   int32_t csz[BINS];                                // cells of class m
   int32_t PA[BINS + 1], PB[BINS + 1];               // occupied levels below a / b
-  int32_t cnt[KS * BINS];                           // cells per (row slice, class)
+  int32_t lane_cells[NT];                           // list build: cells of each lane's rows
   int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
   float redf[4][NT / 64];
   uint64_t redu[NT / 64];
@@ -1247,6 +1246,115 @@ __device__ inline uint8_t* class_table(SolveSmem<BINS, NT, BUDGET>& sm) {
   return reinterpret_cast<uint8_t*>(sm.spare) + (((size_t)sm.R * NT * sm.CS * sizeof(cell_t) + 15) & ~(size_t)15);
 }
 
+// Lanes of the class sweep without a list.  Class q (level A[q]) collects
+// the rows q..nA-1 (a >= A[q]; lower rows never reach class A[q]), so the
+// classes carry nA, nA-1, ..., 1 rows.  With at most c rows per lane, class q
+// gets ceil((nA - q) / c) consecutive lanes; c is the smallest value for
+// which all classes fit in NT lanes (c = 1 when nA (nA + 1) / 2 <= NT).
+struct ClassLanes {
+  int q, k, g, c;  // class index (-1: idle lane), lane within the class, lanes of the class, rows per lane
+};
+
+// sum_{w=1..n} ceil(w / c)
+__device__ inline int lanes_upto(int n, int c) {
+  const int k = n / c, r = n - k * c;
+  return c * (k * (k + 1) / 2) + r * (k + 1);
+}
+
+template <int NT>
+__device__ inline ClassLanes class_lanes(int nA, int t) {
+  ClassLanes r{-1, 0, 1, 1};
+  if (nA <= 0) return r;
+  int lo = 1, hi = nA;  // lanes_upto(nA, nA) = nA <= NT
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (lanes_upto(nA, mid) <= NT)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int c = lo, total = lanes_upto(nA, c);
+  r.c = c;
+  if (t >= total) return r;
+  // first lane of class q: total - lanes_upto(nA - q, c), increasing in q
+  int a = 0, b = nA - 1;
+  while (a < b) {
+    const int mid = (a + b + 1) >> 1;
+    if (total - lanes_upto(nA - mid, c) <= t)
+      a = mid;
+    else
+      b = mid - 1;
+  }
+  r.q = a;
+  r.k = t - (total - lanes_upto(nA - a, c));
+  r.g = (nA - a + c - 1) / c;
+  return r;
+}
+
+// Cell words of a class-list chunk, four at a time.
+template <typename cell_t>
+__device__ __forceinline__ void cells_of(const cell_t* q, uint32_t* e) {
+  if constexpr (sizeof(cell_t) == 2) {
+    const v2u w = *reinterpret_cast<const v2u*>(q);
+    e[0] = w.x & 0xffffu;
+    e[1] = w.x >> 16;
+    e[2] = w.y & 0xffffu;
+    e[3] = w.y >> 16;
+  } else {
+    const v4u w = *reinterpret_cast<const v4u*>(q);
+    e[0] = w.x;
+    e[1] = w.y;
+    e[2] = w.z;
+    e[3] = w.w;
+  }
+}
+
+// sum over s in [s0, s1) of x[s] rho[class], classes one byte each from the
+// table row (4 per word, zero past np); s0 and s1 - s0 multiples of 4, x
+// zero-padded.  Four partial sums (s mod 4) in fixed order; eight cells at a
+// time with all gathers issued before the first product.
+__device__ __forceinline__ float table_dot(const float* x, const uint32_t* trow, const float* rho, int s0, int s1,
+                                           int np) {
+  float a4[4] = {0.f, 0.f, 0.f, 0.f};
+  int s = s0;
+  for (; s + 8 <= s1; s += 8) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const v4u x1 = *reinterpret_cast<const v4u*>(x + s + 4);
+    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
+    const uint32_t c1 = s + 4 < np ? trow[(s >> 2) + 1] : 0u;
+    float r[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = rho[(c0 >> (8 * q)) & 0xffu];
+      r[4 + q] = rho[(c1 >> (8 * q)) & 0xffu];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+    a4[0] = fmaf(__uint_as_float(x1.x), r[4], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x1.y), r[5], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x1.z), r[6], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x1.w), r[7], a4[3]);
+  }
+  if (s < s1) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
+    float r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = rho[(c0 >> (8 * q)) & 0xffu];
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+  }
+  return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+}
+
+// Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
+// the values the next pass works with.
 // Class-major list of the cells (i, j) of A x B whose class has s_m > 0
 // (other classes have rho = 0 and their totals are never used), cut into
 // chunks of exactly C cells (C a multiple of 4; the last chunk of a class
@@ -1261,32 +1369,38 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
   constexpr int MAXCH = 32;  // chunks per class
-  constexpr int RMAX = SolveCore<BINS, NT>::RMAX, KS = SolveCore<BINS, NT>::KS;
+  constexpr int RMAX = SolveCore<BINS, NT>::RMAX;
   static_assert(BINS <= NT * RMAX / 2, "every class must get a chunk");
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
-  // cells per (class, row slice): rows with a >= m, split into KS slices
-  for (int q = t; q < KS * BINS; q += NT) {
-    const int m = q % BINS, k = q / BINS;
-    int c = 0;
-    if (sm.sd[m] > 0.f) {
-      const int r0 = sm.PA[m], nr = nA - r0;
-      const int i0 = r0 + (k * nr) / KS, i1 = r0 + ((k + 1) * nr) / KS;
-      for (int i = i0; i < i1; ++i) {
-        int jlo, jhi;
-        class_run<BINS>(sm, i, m, jlo, jhi);
-        c += jhi - jlo;
-      }
+  // The (class, row) pairs over balanced lanes (class q = A[q] has the rows
+  // q..nA-1), each lane a contiguous range of its class's rows: the lane's
+  // cells, then its rank in the class's row-major order from the lanes before
+  const ClassLanes cl = class_lanes<NT>(nA, t);
+  int mcls = -1, i0 = 0, i1 = 0, mine = 0;
+  if (cl.q >= 0) {
+    mcls = sm.A[cl.q];
+    i0 = cl.q + cl.k * cl.c;
+    i1 = min(i0 + cl.c, nA);
+    for (int i = i0; i < i1; ++i) {
+      int jlo, jhi;
+      class_run_upper<BINS>(sm, i, mcls, jlo, jhi);
+      mine += jhi - jlo;
     }
-    sm.cnt[k * BINS + m] = c;
   }
+  sm.lane_cells[t] = mine;
   for (int u = t; u < RMAX * NT; u += NT) sm.chunk_cls[u] = -1;
+  for (int m = t; m < BINS; m += NT) sm.csz[m] = 0;
+  __syncthreads();
+  int before = 0;
+  if (cl.q >= 0) {
+    for (int x = t - cl.k; x < t; ++x) before += sm.lane_cells[x];
+    if (cl.k == cl.g - 1) sm.csz[mcls] = before + mine;
+  }
   __syncthreads();
   int mx = 0, tot = 0;
   for (int m = t; m < BINS; m += NT) {
-    int c = 0;
-    for (int k = 0; k < KS; ++k) c += sm.cnt[k * BINS + m];
-    sm.csz[m] = c;
+    const int c = sm.csz[m];
     mx = max(mx, c);
     tot += c;
   }
@@ -1368,51 +1482,50 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
     for (int u = 0; u * C < c; ++u) sm.chunk_cls[sm.off[m] + u] = (int16_t)m;
   }
   __syncthreads();
-  // one lane per chunk: the chunk's first cell is cell (u - off[m]) C of
-  // class m in row-major order; find its row slice from the slice counts,
-  // then its row, then write C cells along the class's row runs (a class's
-  // last chunk and the padding chunks are completed with zero cells)
+  // zero cells: padding chunks, and the slots of a class's last chunk past
+  // its cells (chunk u of class m holds the class's cells (u - off[m]) C ..)
   for (int u = t; u < R * NT; u += NT) {
-    cell_t* cp = cells + (size_t)u * CS;
     const int m = sm.chunk_cls[u];
-    int s = 0;
-    if (m >= 0) {
-      int r0 = (u - sm.off[m]) * C;
-      const int n = min(C, sm.csz[m] - r0);
-      int k = 0;
-      while (k < KS - 1 && r0 >= sm.cnt[k * BINS + m]) r0 -= sm.cnt[(k++) * BINS + m];
-      const int rb = sm.PA[m], nr = nA - rb;
-      int i = rb + (k * nr) / KS, jlo = 0, jhi = 0;
-      for (; i < nA; ++i) {
-        class_run<BINS>(sm, i, m, jlo, jhi);
-        if (r0 < jhi - jlo) break;
-        r0 -= jhi - jlo;
-      }
-      int j = jlo + r0;
-      for (; s < n && i < nA; ++s) {
-        cp[s] = (cell_t)(i | (j << SH));
-        if (++j >= jhi) {
-          do {
-            if (++i >= nA) break;
-            class_run<BINS>(sm, i, m, jlo, jhi);
-          } while (jhi <= jlo);
-          j = jlo;
+    const int s0 = m >= 0 ? max(0, min(C, sm.csz[m] - (u - sm.off[m]) * C)) : 0;
+    for (int s = s0; s < C; ++s) cells[(size_t)u * CS + s] = zero_cell;
+  }
+  // this lane's cells from rank `before` on, along its rows' runs
+  if (mine > 0) {
+    int u = sm.off[mcls] + before / C, s = before - (before / C) * C;
+    for (int i = i0; i < i1; ++i) {
+      int jlo, jhi;
+      class_run_upper<BINS>(sm, i, mcls, jlo, jhi);
+      for (int j = jlo; j < jhi; ++j) {
+        cells[(size_t)u * CS + s] = (cell_t)(i | (j << SH));
+        if (++s == C) {
+          s = 0;
+          ++u;
         }
       }
     }
-    for (; s < C; ++s) cp[s] = zero_cell;
   }
   if (sm.tab_lds) {
-    uint8_t* tab = class_table(sm);
-    uint8_t* tabT = tab + nA * sm.nBp;
-    const int nAp = sm.nAp, nBp = sm.nBp;
-    for (int q = t; q < nA * nBp; q += NT) {
-      const int i = q / nBp, j = q - i * nBp;
-      tab[q] = j < nB ? (uint8_t)class_of<BINS>(sm.A[i], sm.B[j]) : (uint8_t)0;
+    // four classes per word; rows padded to nBp (nAp) bytes with class 0
+    uint32_t* tab = reinterpret_cast<uint32_t*>(class_table(sm));
+    uint32_t* tabT = tab + (nA * sm.nBp >> 2);
+    const int wr = sm.nBp >> 2, wc = sm.nAp >> 2;
+    for (int q = t; q < nA * wr; q += NT) {
+      const int i = q / wr, j0 = (q - i * wr) * 4;
+      const int a = sm.A[i];
+      uint32_t w = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (j0 + x < nB) w |= (uint32_t)class_of<BINS>(a, sm.B[j0 + x]) << (8 * x);
+      tab[q] = w;
     }
-    for (int q = t; q < nB * nAp; q += NT) {
-      const int j = q / nAp, i = q - j * nAp;
-      tabT[q] = i < nA ? (uint8_t)class_of<BINS>(sm.A[i], sm.B[j]) : (uint8_t)0;
+    for (int q = t; q < nB * wc; q += NT) {
+      const int j = q / wc, k0 = (q - j * wc) * 4;
+      const int b = sm.B[j];
+      uint32_t w = 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (k0 + x < nA) w |= (uint32_t)class_of<BINS>(sm.A[k0 + x], b) << (8 * x);
+      tabT[q] = w;
     }
   }
   __syncthreads();
@@ -1420,114 +1533,6 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
 
 // Dense copy of the current (L, R) into state[0..2 BINS): level k of L at
 // [k], of R at [BINS + k], 0 at unoccupied levels.
-// Lanes of the class sweep without a list.  Class q (level A[q]) collects
-// the rows q..nA-1 (a >= A[q]; lower rows never reach class A[q]), so the
-// classes carry nA, nA-1, ..., 1 rows.  With at most c rows per lane, class q
-// gets ceil((nA - q) / c) consecutive lanes; c is the smallest value for
-// which all classes fit in NT lanes (c = 1 when nA (nA + 1) / 2 <= NT).
-struct ClassLanes {
-  int q, k, g;  // class index (-1: idle lane), lane within the class, lanes of the class
-};
-
-// sum_{w=1..n} ceil(w / c)
-__device__ inline int lanes_upto(int n, int c) {
-  const int k = n / c, r = n - k * c;
-  return c * (k * (k + 1) / 2) + r * (k + 1);
-}
-
-template <int NT>
-__device__ inline ClassLanes class_lanes(int nA, int t) {
-  ClassLanes r{-1, 0, 1};
-  if (nA <= 0) return r;
-  int lo = 1, hi = nA;  // lanes_upto(nA, nA) = nA <= NT
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (lanes_upto(nA, mid) <= NT)
-      hi = mid;
-    else
-      lo = mid + 1;
-  }
-  const int c = lo, total = lanes_upto(nA, c);
-  if (t >= total) return r;
-  // first lane of class q: total - lanes_upto(nA - q, c), increasing in q
-  int a = 0, b = nA - 1;
-  while (a < b) {
-    const int mid = (a + b + 1) >> 1;
-    if (total - lanes_upto(nA - mid, c) <= t)
-      a = mid;
-    else
-      b = mid - 1;
-  }
-  r.q = a;
-  r.k = t - (total - lanes_upto(nA - a, c));
-  r.g = (nA - a + c - 1) / c;
-  return r;
-}
-
-// Cell words of a class-list chunk, four at a time.
-template <typename cell_t>
-__device__ __forceinline__ void cells_of(const cell_t* q, uint32_t* e) {
-  if constexpr (sizeof(cell_t) == 2) {
-    const v2u w = *reinterpret_cast<const v2u*>(q);
-    e[0] = w.x & 0xffffu;
-    e[1] = w.x >> 16;
-    e[2] = w.y & 0xffffu;
-    e[3] = w.y >> 16;
-  } else {
-    const v4u w = *reinterpret_cast<const v4u*>(q);
-    e[0] = w.x;
-    e[1] = w.y;
-    e[2] = w.z;
-    e[3] = w.w;
-  }
-}
-
-// sum over s in [s0, s1) of x[s] rho[class], classes one byte each from the
-// table row (4 per word, zero past np); s0 and s1 - s0 multiples of 4, x
-// zero-padded.  Four partial sums (s mod 4) in fixed order; eight cells at a
-// time with all gathers issued before the first product.
-__device__ __forceinline__ float table_dot(const float* x, const uint32_t* trow, const float* rho, int s0, int s1,
-                                           int np) {
-  float a4[4] = {0.f, 0.f, 0.f, 0.f};
-  int s = s0;
-  for (; s + 8 <= s1; s += 8) {
-    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
-    const v4u x1 = *reinterpret_cast<const v4u*>(x + s + 4);
-    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
-    const uint32_t c1 = s + 4 < np ? trow[(s >> 2) + 1] : 0u;
-    float r[8];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      r[q] = rho[(c0 >> (8 * q)) & 0xffu];
-      r[4 + q] = rho[(c1 >> (8 * q)) & 0xffu];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
-    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
-    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
-    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
-    a4[0] = fmaf(__uint_as_float(x1.x), r[4], a4[0]);
-    a4[1] = fmaf(__uint_as_float(x1.y), r[5], a4[1]);
-    a4[2] = fmaf(__uint_as_float(x1.z), r[6], a4[2]);
-    a4[3] = fmaf(__uint_as_float(x1.w), r[7], a4[3]);
-  }
-  if (s < s1) {
-    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
-    const uint32_t c0 = s < np ? trow[s >> 2] : 0u;
-    float r[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = rho[(c0 >> (8 * q)) & 0xffu];
-    __builtin_amdgcn_sched_barrier(0);
-    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
-    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
-    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
-    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
-  }
-  return (a4[0] + a4[1]) + (a4[2] + a4[3]);
-}
-
-// Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
-// the values the next pass works with.
 template <int BINS, int NT>
 __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, float sumL, float sumR) {
   for (int k = threadIdx.x; k < BINS; k += NT) {
@@ -1576,7 +1581,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     sm.lc[nA] = 0.f;
     sm.rc[nB] = 0.f;
   }
-  const ClassLanes cl = LIST ? ClassLanes{-1, 0, 1} : class_lanes<NT>(nA, t);
+  const ClassLanes cl = LIST ? ClassLanes{-1, 0, 1, 1} : class_lanes<NT>(nA, t);
   // class list: per round, the first lane of this lane's class in the wave
   // (64: padding chunk) and the class this lane completes (-1: none)
   constexpr int RMAX = SolveCore<BINS, NT>::RMAX;
