@@ -121,6 +121,18 @@ hr_status hr_get_flags(hr_workspace* ws, uint32_t* flags, int32_t clear);
 hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
                         uint32_t* hist_grad_raw, hr_workspace* ws, void* stream);
 
+/* The histograms of hr_build_hist for n images of one bit depth, in one
+ * launch (a grid of tiles per image; the last tile of an image rescales its
+ * gradient histogram).
+ *  in        : host array [n] of image descriptors
+ *  hist_v    : device uint32[n][bins], out: H_C(S) of each image
+ *  hist_grad : device uint32[n][bins], out: H_C(grad S) of each image
+ * n must not exceed the workspace's max_images.  Uses the workspace's
+ * per-image state and descriptor table: calls on one workspace are
+ * stream-ordered (as with hr_enhance_batch). */
+hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
+                              hr_workspace* ws, void* stream);
+
 /* Alg. 1 followed by the reprocessing of Eqs. (17)-(20).
  *  hist_v, hist_grad : device uint32[bins] (as produced by hr_build_hist)
  *  npix              : number of pixels N (= sum of hist_v)

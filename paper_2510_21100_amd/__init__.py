@@ -9,6 +9,7 @@ from .api import (  # noqa: F401
     Workspace,
     workspace,
     build_hist,
+    build_hist_batch,
     solve,
     match,
     enhance,

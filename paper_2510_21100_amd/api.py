@@ -115,6 +115,25 @@ def build_hist(img: torch.Tensor, ws: Workspace | None = None):
     return hv, hg, hraw
 
 
+def build_hist_batch(imgs: Sequence[torch.Tensor], ws: Workspace | None = None):
+    """Histograms of n images (same bit depth) in one launch.  Returns
+    (hist_v, hist_grad) as (n, bins) int32 tensors (counts)."""
+    n = len(imgs)
+    if n == 0:
+        raise ValueError("empty batch")
+    bits = _bits_of(imgs[0])
+    if any(_bits_of(x) != bits for x in imgs):
+        raise ValueError("all images of a batch must have the same bit depth")
+    bins = 1 << bits
+    ws = ws or workspace(max_images=n)
+    dev = imgs[0].device
+    hv = torch.empty((n, bins), dtype=torch.int32, device=dev)
+    hg = torch.empty((n, bins), dtype=torch.int32, device=dev)
+    arr = (HrImage * n)(*[_image(x) for x in imgs])
+    check(lib.hr_build_hist_batch(arr, n, bits, hv.data_ptr(), hg.data_ptr(), ws.handle, _stream()))
+    return hv, hg
+
+
 def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Params = Params(),
           ws: Workspace | None = None):
     """Returns (illum, refl, target) float32 histograms in counts."""

@@ -293,6 +293,43 @@ hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uin
   return HR_OK;
 }
 
+hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
+                              hr_workspace* ws, void* stream) {
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  const int bins = 1 << bits;
+  if (!in || !hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_build_hist_batch: NULL pointer");
+  if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_build_hist_batch: n must be >= 1");
+  std::vector<hr::ImgDesc> descs((size_t)n);
+  int64_t max_npix = 0, total = 0;
+  for (int i = 0; i < n; ++i) {
+    if ((st = make_desc(&in[i], bits, "hr_build_hist_batch", &descs[i]))) return st;
+    max_npix = std::max(max_npix, descs[i].npix);
+    total += descs[i].npix;
+  }
+  if ((st = check_ws(ws, bins))) return st;
+  if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_build_hist_batch: n exceeds the workspace's max_images");
+  // tiles sized on the whole batch: a few per compute unit
+  const int64_t tile_px = plain_tile_px(bits, total, ws->cu_count, 8);
+  const int64_t max_tiles = (max_npix + tile_px - 1) / tile_px;
+  if (max_tiles > (1LL << 31) - 1 || n > 65535) return fail(HR_ERR_UNSUPPORTED, "hr_build_hist_batch: grid too large");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int slot = ws->slot;
+  if (ws->ev_used[slot]) HR_HIP(hipEventSynchronize(ws->ev[slot]));
+  uint8_t* stage = ws->h_stage[slot];
+  std::memcpy(stage, descs.data(), sizeof(hr::ImgDesc) * (size_t)n);
+  auto* desc_d = reinterpret_cast<hr::ImgDesc*>(ws->d_table + sizeof(hr::BatchHeader));
+  HR_HIP(hipMemcpyAsync(desc_d, stage, sizeof(hr::ImgDesc) * (size_t)n, hipMemcpyHostToDevice, s));
+  auto* st_d = reinterpret_cast<hr::ImageState*>(ws->d_state);
+  HR_HIP(hr::launch::fill_u32(hist_v, (int64_t)n * bins, 0, s));
+  HR_HIP(hr::launch::fill_u32(ws->d_state, (int64_t)n * hr::ImageState::words(bins), 0, s));
+  HR_HIP(hr::launch::hist_batch(bits, n, desc_d, max_tiles, tile_px, hist_v, hist_grad, st_d, ws->d_flags, s));
+  HR_HIP(hipEventRecord(ws->ev[slot], s));
+  ws->ev_used[slot] = true;
+  ws->slot = (slot + 1) % kStaging;
+  return HR_OK;
+}
+
 hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix, const hr_params* p,
                    float* illum, float* refl, float* target, hr_workspace* ws, void* stream) {
   hr_status st = check_params(p, 0);

@@ -115,6 +115,36 @@ __device__ inline ImageState* state_of(ImageState* st, int64_t st_words, int i) 
   return reinterpret_cast<ImageState*>(reinterpret_cast<uint32_t*>(st) + i * st_words);
 }
 
+// Histograms of n images in one launch: grid (tiles of the largest image, n);
+// the per-image state holds the raw gradient histogram and the tile ticket.
+template <int BITS>
+__global__ __launch_bounds__(NT_PIX) void k_hist_batch(const ImgDesc* __restrict__ desc, int64_t tile_px,
+                                                       uint32_t* hs, uint32_t* hg, ImageState* st,
+                                                       uint32_t* flags) {
+  constexpr int BINS = Cfg<BITS>::BINS;
+  __shared__ HistSmem<BITS, NT_PIX> sm;
+  __shared__ uint32_t red[NT_PIX / 64];
+  __shared__ uint32_t last;
+  const int i = blockIdx.y;
+  const ImgDesc d = desc[i];
+  const int64_t P0 = (int64_t)blockIdx.x * tile_px;
+  if (P0 >= d.npix) return;  // uniform: this image has fewer tiles
+  const int64_t P1 = min(P0 + tile_px, d.npix);
+  ImageState* s = state_of(st, ImageState::words(BINS), i);
+  uint32_t* graw = s->graw(BINS);
+  hist_tile<BITS, NT_PIX>(d, P0, P1, sm, hs + (size_t)i * BINS, graw);
+  if (threadIdx.x == 0) {
+    if (sm.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
+    fence_release_agent();
+    const uint32_t ntiles = (uint32_t)((d.npix + tile_px - 1) / tile_px);
+    last = (atomicAdd(&s->done, 1u) == ntiles - 1) ? 1u : 0u;
+    if (last) fence_acquire_agent();
+  }
+  __syncthreads();
+  if (!last) return;
+  rebin_gradient<BINS, NT_PIX>(graw, hg + (size_t)i * BINS, sm.hs, red);
+}
+
 // Completes image i once all its histogram items are merged: adds up the
 // partial histograms, rebins the gradient histogram, runs the solver and the
 // LUT, then publishes the LUT.  Everything it needs is re-read from the
@@ -328,6 +358,16 @@ hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint3
   else
     hipLaunchKernelGGL(k_hist<10>, dim3((unsigned)tiles), dim3(NT_PIX), 0, s, d, tile_px, hs, graw, hg, ticket,
                        flags);
+  return hipGetLastError();
+}
+
+hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, int64_t tile_px, uint32_t* hs,
+                      uint32_t* hg, ImageState* st, uint32_t* flags, hipStream_t s) {
+  const dim3 grid((unsigned)max_tiles, (unsigned)n);
+  if (bits == 8)
+    hipLaunchKernelGGL(k_hist_batch<8>, grid, dim3(NT_PIX), 0, s, desc, tile_px, hs, hg, st, flags);
+  else
+    hipLaunchKernelGGL(k_hist_batch<10>, grid, dim3(NT_PIX), 0, s, desc, tile_px, hs, hg, st, flags);
   return hipGetLastError();
 }
 

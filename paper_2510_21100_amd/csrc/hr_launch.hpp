@@ -84,6 +84,8 @@ namespace launch {
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint32_t* graw, uint32_t* hg,
                 uint32_t* ticket, uint32_t* flags, hipStream_t s);
+hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, int64_t tile_px, uint32_t* hs,
+                      uint32_t* hg, ImageState* st, uint32_t* flags, hipStream_t s);
 hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
                  uint32_t* lists, float* illum, float* refl, float* target, uint32_t* flags, hipStream_t s);
 hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut, uint16_t* lut_user,

@@ -86,14 +86,8 @@ class SoftMatchLossFn(torch.autograd.Function):
 
 
 def histograms(images: Sequence[torch.Tensor], ws: api.Workspace):
-    """Stacked (n, 256) int32 H_C(S) and H_C(grad S) of 8-bit images."""
-    hv = torch.empty((len(images), BINS), dtype=torch.int32, device=images[0].device)
-    hg = torch.empty_like(hv)
-    for i, x in enumerate(images):
-        a, b, _ = api.build_hist(x, ws)
-        hv[i].copy_(a)
-        hg[i].copy_(b)
-    return hv, hg
+    """Stacked (n, 256) int32 H_C(S) and H_C(grad S) of 8-bit images (one launch)."""
+    return api.build_hist_batch(list(images), ws)
 
 
 def enhancement_loss(images: Sequence[torch.Tensor], target_imgs: Sequence[torch.Tensor], alpha: torch.Tensor,

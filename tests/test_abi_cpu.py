@@ -83,6 +83,19 @@ def test_build_hist_validation(L):
     assert L.lib.hr_build_hist(C.byref(_img()), 8, None, 0x3000, None, None, None) == L.HR_ERR_INVALID_ARG
 
 
+def test_build_hist_batch_validation(L):
+    arr = (L.HrImage * 2)(_img(), _img(w=0))
+    f = L.lib.hr_build_hist_batch
+    assert f(None, 1, 8, 0x2000, 0x3000, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(arr, 0, 8, 0x2000, 0x3000, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(arr, 1, 8, None, 0x3000, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(arr, 1, 9, 0x2000, 0x3000, None, None) == L.HR_ERR_UNSUPPORTED
+    assert f(arr, 2, 8, 0x2000, 0x3000, None, None) == L.HR_ERR_INVALID_ARG  # second image has width 0
+    assert "width" in _err(L)
+    assert f(arr, 1, 8, 0x2000, 0x3000, None, None) == L.HR_ERR_INVALID_ARG  # no workspace
+    assert "workspace" in _err(L)
+
+
 def _params(L, bins=256, iters=50, alpha=0.01, beta=0.01, gamma=2.2):
     return L.HrParams(bins, iters, alpha, beta, gamma)
 

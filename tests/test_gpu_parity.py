@@ -66,6 +66,26 @@ def test_hist_strided_10bit(H):
     _hist_case(H, img, padded_gpu(img, 3, 2))
 
 
+@pytest.mark.parametrize("bits", [8, 10])
+def test_hist_batch_bit_exact(H, bits):
+    # ragged sizes (ragged tails, width 1, height 1, wide rows) plus a strided
+    # member: every image's histograms equal the oracle's, in one launch
+    shapes = [(256, 256), (13, 31), (1, 37), (29, 1), (3, 5000), (97, 4001)] if bits == 8 else \
+             [(300, 500), (17, 8192), (1, 3), (45, 91)]
+    imgs = [cfg_image(1 if bits == 8 else 4, *sh, bits=bits) for sh in shapes]
+    gpu = [to_gpu(x) for x in imgs]
+    gpu[-1] = padded_gpu(imgs[-1], 5, 1 if bits == 8 else 2)
+    ws = H.Workspace(max_images=len(imgs), max_bins=1 << bits)
+    for rep in range(2):  # a second call reuses the state left by the first
+        hv, hg = H.build_hist_batch(gpu, ws)
+        torch.cuda.synchronize()
+        for i, img in enumerate(imgs):
+            hS, graw, gmax, hG = oracle_hists(img, 1 << bits)
+            assert np.array_equal(to_np(hv[i]).astype(np.int64), hS), (rep, i)
+            assert np.array_equal(to_np(hg[i]).astype(np.int64), hG), (rep, i)
+    ws.close()
+
+
 def _solve_case(H, img, params):
     bins = params.bins
     hS, graw, gmax, hG = oracle_hists(img, bins)
