@@ -1091,6 +1091,8 @@ struct SolveCore {
   float lc[BINS + 4], rc[BINS + 4];                 // current L on A, R on B; [n] = 0
   alignas(16) float l2c[BINS + PAD];                // L^2 on A (zero padded), later L'
   alignas(16) float wc[BINS + PAD];                 // R' R on B (zero padded)
+  alignas(16) float af[BINS + PAD];                 // levels a of A as floats (zero padded)
+  alignas(16) float bq[BINS + PAD];                 // levels b of B over (l-1), FP32 (zero padded)
   float lraw[BINS + 4];                             // L' of Eq. (12) on A, before Eq. (15); [n] = 0
   float rn[BINS + 4];                               // R' of Eq. (13) on B, before Eq. (14); [n] = 0
   double rcum[BINS + 1];                            // running sums of R on B (sweeps without a list)
@@ -1353,6 +1355,51 @@ __device__ __forceinline__ float table_dot(const float* x, const uint32_t* trow,
   return (a4[0] + a4[1]) + (a4[2] + a4[3]);
 }
 
+// sum over s in [s0, s1) of x[s] rho[index(a, b)] with the class computed as
+// trunc(a * (b / (l-1)) + 1/2) in FP32 (u[s] and v are a and b / (l-1), in
+// either order): exact for every a, b < l at l = 256 and 1024, since the
+// rounded product is within 1.3e-4 of a b / (l-1) and that lies at least
+// 1/(2(l-1)) from a half-integer.  s0 and s1 - s0 multiples of 4; x and u
+// zero-padded.  Same shape as table_dot.
+__device__ __forceinline__ float class_dot(const float* x, const float* u, float v, const float* rho, int s0,
+                                           int s1) {
+  float a4[4] = {0.f, 0.f, 0.f, 0.f};
+  int s = s0;
+  for (; s + 8 <= s1; s += 8) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const v4u x1 = *reinterpret_cast<const v4u*>(x + s + 4);
+    const v4u u0 = *reinterpret_cast<const v4u*>(u + s);
+    const v4u u1 = *reinterpret_cast<const v4u*>(u + s + 4);
+    const uint32_t uu[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+    float r[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = rho[(int)fmaf(__uint_as_float(uu[q]), v, 0.5f)];
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+    a4[0] = fmaf(__uint_as_float(x1.x), r[4], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x1.y), r[5], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x1.z), r[6], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x1.w), r[7], a4[3]);
+  }
+  if (s < s1) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const v4u u0 = *reinterpret_cast<const v4u*>(u + s);
+    const uint32_t uu[4] = {u0.x, u0.y, u0.z, u0.w};
+    float r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = rho[(int)fmaf(__uint_as_float(uu[q]), v, 0.5f)];
+    __builtin_amdgcn_sched_barrier(0);
+    a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
+    a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
+    a4[2] = fmaf(__uint_as_float(x0.z), r[2], a4[2]);
+    a4[3] = fmaf(__uint_as_float(x0.w), r[3], a4[3]);
+  }
+  return (a4[0] + a4[1]) + (a4[2] + a4[3]);
+}
+
 // Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
 // the values the next pass works with.
 // Class-major list of the cells (i, j) of A x B whose class has s_m > 0
@@ -1567,6 +1614,10 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   for (int q = t; q < BINS + PAD; q += NT) {
     if (q >= nA) sm.l2c[q] = 0.f;
     if (q >= nB) sm.wc[q] = 0.f;
+    if (!TAB) {
+      sm.af[q] = q < nA ? (float)sm.A[q] : 0.f;
+      sm.bq[q] = q < nB ? (float)sm.B[q] / (float)(BINS - 1) : 0.f;
+    }
   }
   for (int m = t; m < BINS + 4; m += NT) sm.rho[m] = 0.f;
   // the passes start from L' = L(0), R' = R(0) with unit sums (Eqs. 14, 15
@@ -1730,17 +1781,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
           acc = table_dot(sm.l2c, trow, sm.rho, s0, s0 + Lc, nAp);
         } else {
-          const int b = sm.B[o];
-          float a4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-          for (int s = s0; s < s0 + Lc; s += 4) {
-            const v4u xv = *reinterpret_cast<const v4u*>(&sm.l2c[s]);
-            const uint32_t x4[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-              a4[x] = fmaf(__uint_as_float(x4[x]), sm.rho[class_of<BINS>(sm.A[min(s + x, nA - 1)], b)], a4[x]);
-          }
-          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          acc = class_dot(sm.l2c, sm.af, sm.bq[o], sm.rho, s0, s0 + Lc);
         }
         acc = group_sum_last(acc, Gc);
         if (k == Gc - 1 && q / Gc < nB) {
@@ -1770,17 +1811,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
           acc = table_dot(sm.wc, trow, sm.rho, s0, s0 + Lr, nBp);
         } else {
-          const int a = sm.A[o];
-          float a4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-          for (int s = s0; s < s0 + Lr; s += 4) {
-            const v4u xv = *reinterpret_cast<const v4u*>(&sm.wc[s]);
-            const uint32_t x4[4] = {xv.x, xv.y, xv.z, xv.w};
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-              a4[x] = fmaf(__uint_as_float(x4[x]), sm.rho[class_of<BINS>(a, sm.B[min(s + x, nB - 1)])], a4[x]);
-          }
-          acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          acc = class_dot(sm.wc, sm.bq, sm.af[o], sm.rho, s0, s0 + Lr);
         }
         acc = group_sum_last(acc, Gr);
         if (k == Gr - 1 && q / Gr < nA) {
