@@ -1728,26 +1728,54 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         for (int j = t; j <= nB; j += NT) sm.rcum[j] = j < nB ? (double)sm.rn[j] : 0.0;
         __syncthreads();
         block_scan<NT, double>(sm.rcum, nB + 1, sm.redd);
-        double d0 = 0.0, d1 = 0.0;
+        // Run bounds as in class_run_upper, with the class's two numerators
+        // hoisted; four rows per step, each stage's LDS reads issued together.
+        // An empty run has jlo = jhi and adds an exact zero.
+        double d4[4] = {0.0, 0.0, 0.0, 0.0};
         if (cl.q >= 0) {
+          constexpr uint32_t D = BINS - 1;
           const int m = sm.A[cl.q], g = cl.g;
+          const float nlo = m ? (float)((2u * m - 1u) * D) : 0.f, nhi = (float)((2u * m + 1u) * D);
           int i = cl.q + cl.k;
-          for (; i + g < nA; i += 2 * g) {
-            int jlo0, jhi0, jlo1, jhi1;
-            class_run_upper<BINS>(sm, i, m, jlo0, jhi0);
-            class_run_upper<BINS>(sm, i + g, m, jlo1, jhi1);
-            // an empty run has jlo = jhi and adds an exact zero
-            d0 = fma((double)sm.lraw[i], sm.rcum[jhi0] - sm.rcum[jlo0], d0);
-            d1 = fma((double)sm.lraw[i + g], sm.rcum[jhi1] - sm.rcum[jlo1], d1);
+          if (sm.A[i] == 0) {  // a = 0 (then i = 0 and m = 0): the whole row
+            d4[0] = (double)sm.lraw[i] * (sm.rcum[nB] - sm.rcum[0]);
+            i += g;
           }
-          if (i < nA) {
+          for (; i + 3 * g < nA; i += 4 * g) {
+            float inv[4], lv[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              inv[x] = sm.inv2a[i + x * g];
+              lv[x] = sm.lraw[i + x * g];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            int jl[4], jh[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              const uint32_t blo = m ? (uint32_t)(nlo * inv[x]) + 1u : 0u;
+              const uint32_t bhi = min((uint32_t)(nhi * inv[x]), D);
+              jl[x] = sm.PB[blo];
+              jh[x] = sm.PB[max(bhi + 1u, blo)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            double rl[4], rh[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              rl[x] = sm.rcum[jl[x]];
+              rh[x] = sm.rcum[jh[x]];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) d4[x] = fma((double)lv[x], rh[x] - rl[x], d4[x]);
+          }
+          for (; i < nA; i += g) {
             int jlo, jhi;
             class_run_upper<BINS>(sm, i, m, jlo, jhi);
-            d0 = fma((double)sm.lraw[i], sm.rcum[jhi] - sm.rcum[jlo], d0);
+            d4[0] = fma((double)sm.lraw[i], sm.rcum[jhi] - sm.rcum[jlo], d4[0]);
           }
         }
         double* part = reinterpret_cast<double*>(sm.spare);  // NT lane partials
-        part[t] = d0 + d1;
+        part[t] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
         __syncthreads();
         if (cl.q >= 0 && cl.k == 0) {
           double d = 0.0;
