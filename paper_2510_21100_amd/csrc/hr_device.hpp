@@ -1400,8 +1400,6 @@ __device__ __forceinline__ float class_dot(const float* x, const float* u, float
   return (a4[0] + a4[1]) + (a4[2] + a4[3]);
 }
 
-// Dense (L, R) of a checkpoint: L' / sum L' and R' / sum R' (Eqs. 14, 15),
-// the values the next pass works with.
 // Class-major list of the cells (i, j) of A x B whose class has s_m > 0
 // (other classes have rho = 0 and their totals are never used), cut into
 // chunks of exactly C cells (C a multiple of 4; the last chunk of a class
@@ -1578,13 +1576,15 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   __syncthreads();
 }
 
-// Dense copy of the current (L, R) into state[0..2 BINS): level k of L at
-// [k], of R at [BINS + k], 0 at unoccupied levels.
+// Dense (L, R) of a checkpoint into state[0..2 BINS): L' / sum L' and
+// R' / sum R' (Eqs. 14, 15), the values the next pass works with (invL, invR:
+// the reciprocal sums); level k of L at [k], of R at [BINS + k], 0 at
+// unoccupied levels.
 template <int BINS, int NT>
-__device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, float sumL, float sumR) {
+__device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, float invL, float invR) {
   for (int k = threadIdx.x; k < BINS; k += NT) {
-    state[k] = sm.sd[k] > 0.f ? sm.lraw[sm.PA[k]] / sumL : 0.f;
-    state[BINS + k] = sm.PB[k + 1] > sm.PB[k] ? sm.rn[sm.PB[k]] / sumR : 0.f;
+    state[k] = sm.sd[k] > 0.f ? sm.lraw[sm.PA[k]] * invL : 0.f;
+    state[BINS + k] = sm.PB[k + 1] > sm.PB[k] ? sm.rn[sm.PB[k]] * invR : 0.f;
   }
 }
 
@@ -1656,9 +1656,9 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   for (int it = 0; it < p.iters; ++it) {
     // sums of the previous pass's L', R' (Eqs. 14, 15)
     const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
-    const float sumL = sums.x, sumR = sums.y;
+    const float sumL = sums.x, sumR = sums.y, invL = 1.f / sumL, invR = 1.f / sumR;
     if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0)
-      write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS, sumL, sumR);
+      write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS, invL, invR);
     // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m, from the
     // unnormalised L', R': d_m = (sum of L' R' over the class) / (sumL sumR)
     {
@@ -1786,24 +1786,25 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
       }
       float ql = 0.f;
       for (int i = t; i < nA; i += NT) {
-        const float l = sm.lraw[i] / sumL;  // Eq. (15)
+        const float l = sm.lraw[i] * invL;  // Eq. (15)
         sm.lc[i] = l;
         sm.l2c[i] = l * l;
         ql += l * l;
       }
-      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;  // Eq. (14)
+      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] * invR;  // Eq. (14)
       wave_partial<NT>(ql, sm.redf[0]);
     }
     __syncthreads();
     // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta)
     {
-      const float denR = block_read<NT>(sm.redf[0]) + p.beta;
+      const float invD = 1.f / (block_read<NT>(sm.redf[0]) + p.beta);
       float qr = 0.f, sr = 0.f;
       for (int base = 0; base < nB * Gc; base += NT) {
         if (base + (t & ~63) >= nB * Gc) break;  // whole wave past the outputs
         const int q = base + t;
         const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
         const int s0 = k * Lc;  // a multiple of 4
+        const float r = sm.rc[o], bg = p.beta * sm.gc[o];
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
@@ -1813,8 +1814,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         }
         acc = group_sum_last(acc, Gc);
         if (k == Gc - 1 && q / Gc < nB) {
-          const float r = sm.rc[o];
-          const float rn = (r * acc + p.beta * sm.gc[o]) / denR;
+          const float rn = fmaf(r, acc, bg) * invD;
           sm.rn[o] = rn;
           sm.wc[o] = rn * r;
           qr += rn * rn;
@@ -1827,13 +1827,14 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     __syncthreads();
     // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha)
     {
-      const float denL = block_read<NT>(sm.redf[1]) + p.alpha;
+      const float invD = 1.f / (block_read<NT>(sm.redf[1]) + p.alpha);
       float sl = 0.f;
       for (int base = 0; base < nA * Gr; base += NT) {
         if (base + (t & ~63) >= nA * Gr) break;  // whole wave past the outputs
         const int q = base + t;
         const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
         const int s0 = k * Lr;
+        const float lo = sm.lc[o], as = p.alpha * sm.sc[o];
         float acc = 0.f;
         if constexpr (TAB) {
           const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
@@ -1843,7 +1844,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         }
         acc = group_sum_last(acc, Gr);
         if (k == Gr - 1 && q / Gr < nA) {
-          const float ln = (sm.lc[o] * acc + p.alpha * sm.sc[o]) / denL;
+          const float ln = fmaf(lo, acc, as) * invD;
           sm.lraw[o] = ln;
           sl += ln;
         }
@@ -1854,11 +1855,12 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   }
   // Eqs. (15), (14) of the last pass
   {
-    const float sumL = block_read<NT>(sm.redf[3]), sumR = block_read<NT>(sm.redf[2]);
+    const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
+    const float invL = 1.f / sums.x, invR = 1.f / sums.y;
     if (ckpt && p.ckpt_every > 0 && p.iters % p.ckpt_every == 0)
-      write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS, sumL, sumR);
-    for (int i = t; i < nA; i += NT) sm.lc[i] = sm.lraw[i] / sumL;
-    for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] / sumR;
+      write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS, invL, invR);
+    for (int i = t; i < nA; i += NT) sm.lc[i] = sm.lraw[i] * invL;
+    for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] * invR;
   }
   __syncthreads();
 }
