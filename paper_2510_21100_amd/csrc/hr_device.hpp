@@ -102,6 +102,7 @@ __device__ inline void set_lane(uint32_t (&w)[N], int k, uint32_t v) {
 // that the row mask enables.  Lanes without a source read zero.
 namespace dpp {
 constexpr int ROW_SHR = 0x110;  // + n, n = 1..15
+constexpr int WAVE_SHL1 = 0x130;  // lane i takes lane i + 1 (lane 63: zero)
 constexpr int BCAST15 = 0x142;
 constexpr int BCAST31 = 0x143;
 }  // namespace dpp
@@ -709,19 +710,50 @@ struct HistTileSplit {
 
   // consumer: gradient of the pixels [at, min(at + STEP, P1))
   __device__ void grad_step(int64_t at) {
+    static_assert(NV == 4 && PX * ESZ == 16, "one 16-byte ring chunk per thread");
+    const uint8_t* ringb = reinterpret_cast<const uint8_t*>(sm.ring);
     const int64_t dend = min(at + STEP, P1);
     const int64_t q = at + (int64_t)tt * PX;
     const int n = (int)max((int64_t)0, min((int64_t)PX, dend - q));
+    // Own chunk: q - P0 is a multiple of PX, so the chunk is one aligned
+    // 16-byte read (consecutive lanes, consecutive chunks: no bank
+    // conflicts).  Its right neighbour is the next lane's first pixel (the
+    // last lane of the wave reads it from the ring).  All lanes take part.
+    const uint32_t boff = (uint32_t)(((q - P0) & (RING - 1)) * ESZ);
+    const v4u ov = *reinterpret_cast<const v4u*>(ringb + boff);
+    const uint32_t own[NV] = {ov.x, ov.y, ov.z, ov.w};
+    uint32_t right_last = dpp_get<dpp::WAVE_SHL1, 0xf>(own[0]);
+    if ((threadIdx.x & 63) == 63) right_last = reinterpret_cast<const uint32_t*>(ringb + boff + 16)[0];
+    right_last &= ESZ == 1 ? 0xffu : 0xffffu;
     if (n > 0) {
-      const uint32_t boff = (uint32_t)(((q - P0) & (RING - 1)) * ESZ);
-      uint32_t own[NV];
-      ring_read<NV>(sm.ring, boff, own);
-      const uint32_t rboff = boff + PX * ESZ;
-      const uint32_t right_last = ESZ == 1 ? (uint32_t)reinterpret_cast<const uint8_t*>(sm.ring)[rboff]
-                                           : (uint32_t)reinterpret_cast<const uint16_t*>(sm.ring)[rboff >> 1];
+      // Chunk one row down: it starts W pixels on, at the same byte offset
+      // mod 16 in every lane (W ESZ mod 16), so two aligned 16-byte reads
+      // and a shift by that wave-uniform offset.
       const uint32_t dboff = (uint32_t)(((q + W - P0) & (RING - 1)) * ESZ);
+      const uint32_t dbase = dboff & ~15u, sh = dboff & 3u;
+      const int dsel = __builtin_amdgcn_readfirstlane((int)((dboff >> 2) & 3u));
+      const v4u d0 = *reinterpret_cast<const v4u*>(ringb + dbase);
+      const v4u d1 = *reinterpret_cast<const v4u*>(ringb + dbase + 16);
+      const uint32_t w8[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
       uint32_t dn[NV];
-      ring_read<NV>(sm.ring, dboff, dn);
+      switch (dsel) {
+        case 0:
+#pragma unroll
+          for (int k = 0; k < NV; ++k) dn[k] = __builtin_amdgcn_alignbyte(w8[k + 1], w8[k], sh);
+          break;
+        case 1:
+#pragma unroll
+          for (int k = 0; k < NV; ++k) dn[k] = __builtin_amdgcn_alignbyte(w8[k + 2], w8[k + 1], sh);
+          break;
+        case 2:
+#pragma unroll
+          for (int k = 0; k < NV; ++k) dn[k] = __builtin_amdgcn_alignbyte(w8[k + 3], w8[k + 2], sh);
+          break;
+        default:
+#pragma unroll
+          for (int k = 0; k < NV; ++k) dn[k] = __builtin_amdgcn_alignbyte(w8[k + 4], w8[k + 3], sh);
+          break;
+      }
       if (n == PX && N - W - q >= PX && W > PX) {
 #pragma unroll
         for (int i = 0; i < PX; ++i) {

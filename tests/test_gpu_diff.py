@@ -120,7 +120,7 @@ def test_softmatch_loss_and_target_gradient(H):
         cos = float(got @ ref / (np.linalg.norm(got) * np.linalg.norm(ref)))
         assert cos >= 0.9999, (i, cos)
         assert _rel_inf(got, ref) <= GRAD_REL, i
-    assert abs(float(loss) - np.mean(ref_losses)) <= 1e-5 * np.mean(ref_losses)
+    assert abs(float(loss.detach()) - np.mean(ref_losses)) <= 1e-5 * np.mean(ref_losses)
     ws.close()
 
 
@@ -168,7 +168,7 @@ def test_enhancement_loss_end_to_end(H):
         ref = r["dtarget"] / n
         cos = float(got @ ref / (np.linalg.norm(got) * np.linalg.norm(ref)))
         assert cos >= 0.9999, (i, cos)
-    assert abs(float(loss) - ref_loss) <= 1e-4 * ref_loss
+    assert abs(float(loss.detach()) - ref_loss) <= 1e-4 * ref_loss
     assert abs(float(alpha.grad) - ref_da) <= GRAD_REL * abs(ref_da), (float(alpha.grad), ref_da)
     assert abs(float(beta.grad) - ref_db) <= GRAD_REL * abs(ref_db), (float(beta.grad), ref_db)
 
