@@ -57,9 +57,11 @@ size_t diff_bytes(int max_images) {
   return diff_map_bytes(max_images) + sizeof(unsigned long long) * (kDiffBins + 1) * (size_t)max_images;
 }
 
+// descriptor table: BatchHeader, ImgDesc[max_images], ImgCounters[max_images]
 size_t table_bytes(int max_images) {
-  return sizeof(hr::BatchHeader) + (size_t)max_images * sizeof(hr::ImgDesc);
+  return sizeof(hr::BatchHeader) + (size_t)max_images * (sizeof(hr::ImgDesc) + sizeof(hr::ImgCounters));
 }
+size_t counters_offset(int max_images) { return sizeof(hr::BatchHeader) + (size_t)max_images * sizeof(hr::ImgDesc); }
 
 struct GraphEntry {
   bool valid = false;
@@ -81,8 +83,11 @@ struct hr_workspace {
   uint16_t* d_lut = nullptr;     // plain: LUT scratch [max_bins]
   uint32_t* d_lists = nullptr;   // per image: 3 * bins^2 words of solver lists
   int64_t lists_words = 0;       // words per image slot
-  uint8_t* d_table = nullptr;    // BatchHeader + ImgDesc[max_images]
+  uint8_t* d_table = nullptr;    // BatchHeader + ImgDesc[max_images] + ImgCounters[max_images]
   uint32_t* d_state = nullptr;   // ImageState per image
+  // d_state's partial slots are zero in the layout of this bit depth (0: all
+  // of d_state is zero, -1: unknown)
+  int state_clean_bits = 0;
   uint8_t* d_diff = nullptr;     // differentiated form: soft map [max_images][256] float, sums [max_images][257] u64
   uint8_t* h_stage[kStaging] = {nullptr, nullptr};
   hipEvent_t ev[kStaging] = {nullptr, nullptr};
@@ -324,6 +329,8 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
   HR_HIP(hr::launch::fill_u32(hist_v, (int64_t)n * bins, 0, s));
   HR_HIP(hr::launch::fill_u32(ws->d_state, (int64_t)n * hr::ImageState::words(bins), 0, s));
   HR_HIP(hr::launch::hist_batch(bits, n, desc_d, max_tiles, tile_px, hist_v, hist_grad, st_d, ws->d_flags, s));
+  // images < n: slots zero in this layout; the rest as before
+  ws->state_clean_bits = (ws->state_clean_bits == 0 || ws->state_clean_bits == bits) ? bits : -1;
   HR_HIP(hipEventRecord(ws->ev[slot], s));
   ws->ev_used[slot] = true;
   ws->slot = (slot + 1) % kStaging;
@@ -402,6 +409,8 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     if (tiles + rtiles > (1LL << 30)) return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch: too many tiles");
     sd[k] = d;
   }
+  // per-image counters start at zero on every call (uploaded with the table)
+  std::memset(stage + counters_offset(ws->max_images), 0, sizeof(hr::ImgCounters) * (size_t)n);
   hr::BatchHeader hdr{};
   hdr.n = n;
   hdr.total_tiles = (int32_t)tiles;
@@ -422,14 +431,14 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     }
     auto* hdr_d = reinterpret_cast<hr::BatchHeader*>(ws->d_table);
     auto* desc_d = reinterpret_cast<hr::ImgDesc*>(ws->d_table + sizeof(hr::BatchHeader));
+    auto* ctr_d = reinterpret_cast<hr::ImgCounters*>(ws->d_table + counters_offset(ws->max_images));
     auto* st_d = reinterpret_cast<hr::ImageState*>(ws->d_state);
     hipGraph_t graph = nullptr;
     HR_HIP(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = hipMemcpyAsync(ws->d_table, stage, table_bytes(ws->max_images), hipMemcpyHostToDevice, ws->capture);
-    hipError_t e2 = e1 == hipSuccess ? hr::launch::batch_reset(hdr_d, st_d, bins, ws->capture) : e1;
-    hipError_t e3 = e2 == hipSuccess ? hr::launch::batch(bits, grid, hdr_d, desc_d, st_d, ws->d_lists,
+    hipError_t e3 = e1 == hipSuccess ? hr::launch::batch(bits, grid, hdr_d, desc_d, ctr_d, st_d, ws->d_lists,
                                                         3LL * bins * bins, ws->d_flags, ws->capture)
-                                     : e2;
+                                     : e1;
     hipError_t e4 = hipStreamEndCapture(ws->capture, &graph);
     if (e3 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -443,6 +452,11 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     g.bits = bits;
     g.grid = grid;
   }
+  if (ws->state_clean_bits != 0 && ws->state_clean_bits != bits) {
+    // another layout left data where this one's partial slots are
+    HR_HIP(hr::launch::fill_u32(ws->d_state, hr::ImageState::words(ws->max_bins) * ws->max_images, 0, s));
+  }
+  ws->state_clean_bits = bits;
   HR_HIP(hipGraphLaunch(g.exec, s));
   HR_HIP(hipEventRecord(ws->ev[slot], s));
   ws->ev_used[slot] = true;

@@ -2,10 +2,11 @@
 //
 // One-image form: fill -> hist (last workgroup rescales the gradient
 // histogram) -> solve (one workgroup) -> lut (one workgroup) -> remap.
-// Batched form: one persistent kernel over a shared work queue holding every
-// histogram tile of every image (largest image first) followed by every remap
-// tile; the workgroup that finishes the last histogram tile of an image runs
-// that image's solve and LUT and publishes it; remap tiles wait for it.
+// Batched form: one persistent kernel; workgroups take the histogram tiles of
+// every image from one queue (largest image first); the workgroup that
+// finishes the last histogram tile of an image runs that image's solve and
+// LUT and appends the image to a ready list; remap tiles are then taken image
+// by image in the order of that list.
 #include "hr_device.hpp"
 #include "hr_launch.hpp"
 
@@ -96,19 +97,6 @@ union BatchSmem {
   float2 tab[Cfg<BITS>::BINS];
 };
 
-__global__ void k_batch_reset(BatchHeader* hdr, ImageState* st, int bins) {
-  const int n = hdr->n;
-  const int64_t words = (int64_t)n * ImageState::words(bins);
-  uint32_t* base = reinterpret_cast<uint32_t*>(st);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
-       i += (int64_t)gridDim.x * blockDim.x)
-    base[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    hdr->next = 0;
-    hdr->rhead = 0;
-    hdr->nready = 0;
-  }
-}
 
 
 __device__ inline ImageState* state_of(ImageState* st, int64_t st_words, int i) {
@@ -150,9 +138,9 @@ __global__ __launch_bounds__(NT_PIX) void k_hist_batch(const ImgDesc* __restrict
 // LUT, then publishes the LUT.  Everything it needs is re-read from the
 // tables, so nothing of the item loop stays live across the solver.
 template <int BITS>
-__device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImageState* st, int64_t st_words, int i,
-                             uint32_t* lists_base, int64_t lists_stride, uint32_t* flags, BatchSmem<BITS>& sm,
-                             uint32_t* red) {
+__device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
+                             int64_t st_words, int i, uint32_t* lists_base, int64_t lists_stride, uint32_t* flags,
+                             BatchSmem<BITS>& sm, uint32_t* red) {
   constexpr int BINS = Cfg<BITS>::BINS;
   ImageState* s = state_of(st, st_words, i);
   uint32_t* hs = s->hs();
@@ -161,8 +149,10 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImageState* 
   for (int k = threadIdx.x; k < 3 * BINS; k += NT_BATCH) {
     uint32_t v = 0;
 #pragma unroll
-    for (int q = 0; q < ImageState::NSLOT; ++q)
+    for (int q = 0; q < ImageState::NSLOT; ++q) {
       v += __hip_atomic_load(to_global(s->slot(BINS, q)) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s->slot(BINS, q)[k] = 0u;  // zero for the next call (no other workgroup touches them now)
+    }
     if (k < BINS) hs[k] = v;
     else if (k < 3 * BINS - 1) graw[k - BINS] = v;
   }
@@ -195,11 +185,9 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImageState* 
   drain_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(to_global(&s->ready), 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     // append to the ready list: position by arrival, entry = image + 1
     const uint32_t pos = atomicAdd(&hdr->nready, 1u);
-    __hip_atomic_store(to_global(&state_of(st, st_words, (int)pos)->fifo), (uint32_t)i + 1u, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(to_global(&ctr[pos].fifo), (uint32_t)i + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -218,8 +206,8 @@ __device__ inline int image_of_item(const ImgDesc* desc, int n, int it) {
 // waiting while the head's position is not yet written.  img = -1 once every
 // image is claimed out.  Every image has at least one histogram item, so every
 // position of the list is written in the end.
-__device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImageState* st, int64_t st_words, int n,
-                                   int& img, int& tl) {
+__device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, int n, int& img,
+                                   int& tl) {
   for (;;) {
     const uint32_t pos = __hip_atomic_load(to_global(&hdr->rhead), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (pos >= (uint32_t)n) {
@@ -227,14 +215,13 @@ __device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImageS
       tl = -1;
       return;
     }
-    const uint32_t v = __hip_atomic_load(to_global(&state_of(st, st_words, (int)pos)->fifo), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t v = __hip_atomic_load(to_global(&ctr[pos].fifo), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (v == 0u) {  // published position not written yet
       __builtin_amdgcn_s_sleep(2);
       continue;
     }
     const int c = (int)v - 1;
-    const uint32_t t = atomicAdd(&state_of(st, st_words, c)->rnext, 1u);
+    const uint32_t t = atomicAdd(&ctr[c].rnext, 1u);
     if (t < (uint32_t)desc[c].rtiles) {
       img = c;
       tl = (int)t;
@@ -248,8 +235,8 @@ __device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImageS
 
 template <int BITS>
 __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgDesc* __restrict__ desc,
-                                                    ImageState* st, uint32_t* lists_base, int64_t lists_stride,
-                                                    uint32_t* flags) {
+                                                    ImgCounters* ctr, ImageState* st, uint32_t* lists_base,
+                                                    int64_t lists_stride, uint32_t* flags) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ BatchSmem<BITS> sm;
   __shared__ uint32_t red[NT_BATCH / 64];
@@ -279,12 +266,12 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
     if (threadIdx.x == 0) {
       if (sm.hist.clamped) atomicOr(flags, FLAG_VALUE_CLAMPED);
       fence_release_agent();
-      const bool last = atomicAdd(&s->done, 1u) == (uint32_t)d.ntiles - 1;
+      const bool last = atomicAdd(&ctr[i].done, 1u) == (uint32_t)d.ntiles - 1;
       if (last) fence_acquire_agent();
       last_s = last ? 1u : 0u;
     }
     __syncthreads();
-    if (last_s) finish_image<BITS>(hdr, desc, st, st_words, i, lists_base, lists_stride, flags, sm, red);
+    if (last_s) finish_image<BITS>(hdr, desc, ctr, st, st_words, i, lists_base, lists_stride, flags, sm, red);
     __syncthreads();
   }
   // Remap items, images in the order their LUTs were published, so that no
@@ -301,12 +288,12 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
         img = cur;
         tl = (int)ahead;
       } else {
-        claim_remap(hdr, desc, st, st_words, nimg, img, tl);
+        claim_remap(hdr, desc, ctr, nimg, img, tl);
       }
       item_s = img;
       last_s = (uint32_t)tl;
       cur = img;
-      ahead = img >= 0 ? atomicAdd(&state_of(st, st_words, img)->rnext, 1u) : 0xffffffffu;
+      ahead = img >= 0 ? atomicAdd(&ctr[img].rnext, 1u) : 0xffffffffu;
     }
     lds_wait();
     bare_barrier();
@@ -401,19 +388,15 @@ hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lu
   return hipGetLastError();
 }
 
-hipError_t batch_reset(BatchHeader* hdr, ImageState* st, int bins, hipStream_t s) {
-  // fixed grid: the image count is read on the device, so a captured launch
-  // serves any batch
-  hipLaunchKernelGGL(k_batch_reset, dim3(512), dim3(256), 0, s, hdr, st, bins);
-  return hipGetLastError();
-}
 
-hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImageState* st, uint32_t* lists,
-                 int64_t lists_stride, uint32_t* flags, hipStream_t s) {
+hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
+                 uint32_t* lists, int64_t lists_stride, uint32_t* flags, hipStream_t s) {
   if (bits == 8)
-    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, st, lists, lists_stride, flags);
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, lists_stride,
+                       flags);
   else
-    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, st, lists, lists_stride, flags);
+    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, lists_stride,
+                       flags);
   return hipGetLastError();
 }
 

@@ -59,16 +59,25 @@ struct BatchHeader {
   BatchOut out;
 };
 
+// Per-image counters of the batched form.  They sit in the descriptor table
+// after the ImgDesc array and are uploaded as zeros with it on every call.
+struct ImgCounters {
+  uint32_t done;   // histogram items merged so far
+  uint32_t fifo;   // ready list: entry at this position = published image + 1 (0: not yet)
+  uint32_t rnext;  // remap tiles of this image claimed so far
+  uint32_t pad;
+};
+
 // Per-image device state of the batched form, `words(bins)` 32-bit words.
+// The partial slots are zero between calls: the workgroup that adds them up
+// clears them again.
 // Histogram items merge into one of NSLOT partial histograms (item mod
 // NSLOT), which spreads their atomics; the workgroup that merges the image's
 // last item adds the slots up in slot order.
 struct ImageState {
   static constexpr int NSLOT = 8;
-  uint32_t done;   // histogram items merged so far
-  uint32_t ready;  // LUT published
-  uint32_t fifo;   // ready list, position = this image's index: published image + 1 (0: not yet)
-  uint32_t rnext;  // remap tiles of this image claimed so far
+  uint32_t done;   // hr_build_hist_batch: histogram tiles merged so far
+  uint32_t pad[3];
   static constexpr int64_t words(int bins) { return 4 + 5 * (int64_t)bins + bins / 2 + NSLOT * 3LL * bins; }
   __host__ __device__ uint32_t* base() { return reinterpret_cast<uint32_t*>(this); }
   __host__ __device__ uint32_t* hs() { return base() + 4; }
@@ -91,9 +100,8 @@ hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix,
 hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut, uint16_t* lut_user,
                hipStream_t s);
 hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lut, hipStream_t s);
-hipError_t batch_reset(BatchHeader* hdr, ImageState* st, int bins, hipStream_t s);
-hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImageState* st, uint32_t* lists,
-                 int64_t lists_stride, uint32_t* flags, hipStream_t s);
+hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
+                 uint32_t* lists, int64_t lists_stride, uint32_t* flags, hipStream_t s);
 int step_px(int bits);
 int batch_step_px(int bits);
 int max_width(int bits);
