@@ -355,7 +355,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": measured_traffic(args.workload, bits),
-            "kernel": f"k_batch<{bits}> (graph: descriptor copy + state reset + persistent kernel)",
+            "kernel": f"k_batch<{bits}> (graph: descriptor copy + persistent kernel)",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
         },
