@@ -66,6 +66,31 @@ def test_batch_graph_replay_changing_batches(H):
     ws.close()
 
 
+def test_batch_state_across_bit_depths_and_calls(H):
+    """One workspace: 8-bit and 10-bit batches of changing sizes, with the
+    histogram-only batch call in between.  The per-image partial histograms
+    are cleared by the workgroup that sums them (and fully when the bit depth
+    changes), so every call must equal the one-image path."""
+    ws = H.Workspace(max_images=6, max_bins=1024)
+    b8 = _batch_imgs(SHAPES[:5])
+    b10 = _batch_imgs([(216, 384), (61, 700), (400, 33), (7, 9)], bits=10, cfg=4)
+    g8 = [to_gpu(x) for x in b8]
+    g10 = [to_gpu(x) for x in b10]
+    steps = [("8", g8), ("10", g10[:2]), ("8", g8[:2]), ("8", g8), ("hist", g8[:3]), ("8", g8),
+             ("10", g10), ("hist", g10[:1]), ("10", g10), ("8", g8[1:4])]
+    for k, (what, gimgs) in enumerate(steps):
+        if what == "hist":
+            hv, hg = H.build_hist_batch(gimgs, ws)
+            torch.cuda.synchronize()
+            for i, g in enumerate(gimgs):
+                a, b, _ = H.build_hist(g)
+                torch.cuda.synchronize()
+                assert torch.equal(hv[i], a) and torch.equal(hg[i], b), (k, i)
+        else:
+            _compare_to_plain(H, None, gimgs, H.Params(bins=256 if what == "8" else 1024), ws=ws)
+    ws.close()
+
+
 def test_batch_schedules_agree(H):
     imgs = _batch_imgs(SHAPES[:5])
     gimgs = [to_gpu(x) for x in imgs]
