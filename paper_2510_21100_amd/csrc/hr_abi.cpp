@@ -403,7 +403,6 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     d.ntiles = (int32_t)((d.npix + tile_px - 1) / tile_px);
     d.tile0 = (int32_t)tiles;
     d.rtiles = (int32_t)((d.npix + rtile_px - 1) / rtile_px);
-    d.rtile0 = (int32_t)rtiles;
     tiles += d.ntiles;
     rtiles += d.rtiles;
     if (tiles + rtiles > (1LL << 30)) return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch: too many tiles");
@@ -414,7 +413,6 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   hr::BatchHeader hdr{};
   hdr.n = n;
   hdr.total_tiles = (int32_t)tiles;
-  hdr.total_rtiles = (int32_t)rtiles;
   hdr.tile_px = tile_px;
   hdr.rtile_px = rtile_px;
   hdr.params = solve_params(p);

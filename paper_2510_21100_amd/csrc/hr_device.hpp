@@ -1164,45 +1164,14 @@ __device__ inline int class_of(int a, int b) {
   return (int)((2u * (uint32_t)a * (uint32_t)b + D) / (2u * D));
 }
 
-// floor(x / y) from a float reciprocal of y, corrected to the exact value
-// (the estimate is within one of it for x < 2^22).
-__device__ inline uint32_t div_floor(uint32_t x, uint32_t y, float inv_y) {
-  uint32_t q = (uint32_t)((float)x * inv_y);
-  if ((q + 1u) * y <= x) ++q;
-  if (q * y > x) --q;
-  return q;
-}
-
-// Reflectance levels b of class m in illumination row a = A[i]: the b with
+// Reflectance levels b of class m in illumination row a = A[i], for a >= m
+// (the only rows that reach class m): the b with
 // (2m-1)(l-1) < 2ab < (2m+1)(l-1), as a compacted index range [jlo, jhi) of
-// B.  Both bounds are odd multiples of l-1 over an even number, never
-// integers, so the floors below are the exact bounds.
-template <int BINS, typename SM>
-__device__ inline void class_run(const SM& sm, int i, int m, int& jlo, int& jhi) {
-  constexpr uint32_t D = BINS - 1;
-  const int a = sm.A[i];
-  if (a == 0) {
-    jlo = 0;
-    jhi = m == 0 ? sm.nB : 0;
-    return;
-  }
-  const uint32_t two_a = 2u * (uint32_t)a;
-  const float inv = sm.inv2a[i];
-  const uint32_t blo = m == 0 ? 0u : div_floor((2u * m - 1u) * D, two_a, inv) + 1u;
-  const uint32_t bhi = min(div_floor((2u * m + 1u) * D, two_a, inv), (uint32_t)(BINS - 1));
-  if (blo > bhi) {
-    jlo = jhi = 0;
-    return;
-  }
-  jlo = sm.PB[blo];
-  jhi = sm.PB[bhi + 1];
-}
-
-// class_run for a row with a >= m, as in the class sweep.  There
-// (2m +- 1)(l-1) / 2a lies below 1.5 (l-1) and at least 1/2a from an
-// integer, and the FP32 product with the rounded reciprocal is within
-// 2^-23 relative, under 2e-4: truncation is the exact floor, no correction
-// (checked for every a and m <= a at l = 256 and 1024).
+// B (jlo = jhi: empty).  Both bounds (2m +- 1)(l-1) / 2a are odd multiples of
+// l-1 over an even number, so they lie at least 1/2a from an integer, and
+// below 1.5 (l-1); the FP32 product with the rounded reciprocal 1/2a is within
+// 2^-23 relative, under 2e-4, so truncation gives the exact floors (checked
+// for every a and m <= a at l = 256 and 1024).
 template <int BINS, typename SM>
 __device__ inline void class_run_upper(const SM& sm, int i, int m, int& jlo, int& jhi) {
   constexpr uint32_t D = BINS - 1;
@@ -1438,8 +1407,8 @@ __device__ __forceinline__ float class_dot(const float* x, const float* u, float
 // padded with a cell pointing at zeros).  Chunks are laid out over R rounds of
 // NT lanes; the chunks of a class are consecutive and never cross a 64-chunk
 // boundary, so a class is summed inside one wave of one round.  Within a
-// class the cells are ordered by row slice, row and column.  Chunk u holds
-// its cells contiguously from u * CS.  256 levels only.
+// class the cells are ordered by row and column.  Chunk u holds its cells
+// contiguously from u * CS.  256 levels only.
 template <int BINS, int NT, int BUDGET>
 __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells,
                                  int64_t gcap) {

@@ -22,9 +22,7 @@ struct ImgDesc {
   int32_t ntiles;   // batched form: histogram items of this image
   int32_t tile0;    // batched form: first histogram item of this image
   int32_t rtiles;   // batched form: remap items of this image
-  int32_t rtile0;   // batched form: first remap item of this image
   int32_t slot;     // batched form: index of this image in the caller's arrays
-  int32_t pad;
 };
 
 // Solver parameters as the kernels take them.
@@ -45,14 +43,13 @@ struct BatchOut {
 };
 
 // Header of the batched descriptor table (device copy written per call, so a
-// captured launch graph serves every call).
+// captured launch graph serves every call; the cursors arrive as zeros).
 struct BatchHeader {
-  uint32_t next;         // histogram-item cursor (reset on the device each call)
-  uint32_t rhead;        // ready-list position being remapped (reset each call)
+  uint32_t next;         // histogram-item cursor
+  uint32_t rhead;        // ready-list position being remapped
   int32_t n;             // images in this call
   int32_t total_tiles;   // histogram items over all images
-  int32_t total_rtiles;  // remap items over all images
-  uint32_t nready;       // images in the ready list (reset each call)
+  uint32_t nready;       // images in the ready list
   int64_t tile_px;       // pixels per histogram item (multiple of the pixel step)
   int64_t rtile_px;      // pixels per remap item (multiple of the pixel step)
   SolveParams params;
