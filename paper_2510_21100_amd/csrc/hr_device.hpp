@@ -438,6 +438,35 @@ __device__ inline uint32_t grad_l1(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_sad_u16(a, b, __builtin_amdgcn_sad_u16(c, b, 0u));
 }
 
+using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+
+// max of two pairs of 16-bit lanes (one packed instruction)
+__device__ inline uint32_t max_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                 __builtin_bit_cast(u16x2, b)));
+}
+
+// V of 16 interleaved 8-bit RGB pixels (12 dwords): byte permutes gather R, G
+// and B of two pixels into 16-bit lane pairs, two packed maxima give their V.
+// v[i] gets V of pixel i; packed[q] the V of pixels 4q..4q+3 as bytes.
+__device__ inline void values_packed_8(const uint32_t (&w)[12], uint32_t (&v)[16], uint32_t (&packed)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t d0 = w[3 * q], d1 = w[3 * q + 1], d2 = w[3 * q + 2];
+    // selector bytes: 0-3 pick bytes of the second operand, 4-7 of the first, 0x0c a zero
+    const uint32_t r01 = __builtin_amdgcn_perm(d1, d0, 0x0c030c00u), g01 = __builtin_amdgcn_perm(d1, d0, 0x0c040c01u),
+                   b01 = __builtin_amdgcn_perm(d1, d0, 0x0c050c02u);
+    const uint32_t r23 = __builtin_amdgcn_perm(d2, d1, 0x0c050c02u), g23 = __builtin_amdgcn_perm(d2, d1, 0x0c060c03u),
+                   b23 = __builtin_amdgcn_perm(d2, d1, 0x0c070c04u);
+    const uint32_t v01 = max_u16x2(max_u16x2(r01, g01), b01), v23 = max_u16x2(max_u16x2(r23, g23), b23);
+    packed[q] = __builtin_amdgcn_perm(v23, v01, 0x06040200u);
+    v[4 * q] = v01 & 0xffffu;
+    v[4 * q + 1] = v01 >> 16;
+    v[4 * q + 2] = v23 & 0xffffu;
+    v[4 * q + 3] = v23 >> 16;
+  }
+}
+
 // Chunks (PX pixels of one thread, NW dwords) kept in flight per thread by
 // the pixel loops: enough bytes per CU to cover the HBM latency.
 //
@@ -686,13 +715,22 @@ struct HistTileSplit {
     const int n = (int)max((int64_t)0, min((int64_t)PX, E - p));
     if (n <= 0) return;
     uint32_t v[PX];
-    if (have) values_of_words<BITS, PX, NW>(w, v, clamped);
-    else load_values<BITS, NH>(d, p, n, v, clamped);
     uint32_t packed[NV];
+    bool done_v = false;
+    if constexpr (BITS == 8 && PX == 16 && NW == 12 && NV == 4) {
+      if (have) {
+        values_packed_8(w, v, packed);
+        done_v = true;
+      }
+    }
+    if (!done_v) {
+      if (have) values_of_words<BITS, PX, NW>(w, v, clamped);
+      else load_values<BITS, NH>(d, p, n, v, clamped);
 #pragma unroll
-    for (int q = 0; q < NV; ++q) packed[q] = 0;
+      for (int q = 0; q < NV; ++q) packed[q] = 0;
 #pragma unroll
-    for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
+      for (int i = 0; i < PX; ++i) set_lane<pix_t>(packed, i, v[i]);
+    }
     const uint32_t boff = (uint32_t)(((p - P0) & (RING - 1)) * ESZ);
     ring_write<NV>(sm.ring, boff, packed);
     if (boff < 64) ring_write<NV>(sm.ring, RING_BYTES + boff, packed);
@@ -755,11 +793,28 @@ struct HistTileSplit {
           break;
       }
       if (n == PX && N - W - q >= PX && W > PX) {
+        if constexpr (BITS == 8) {
+          // |right - own| + |down - own| of four pixels per dword: one byte
+          // permute packs (right, down) as 16-bit lanes, one packs (own,
+          // own), and one SAD adds both differences
 #pragma unroll
-        for (int i = 0; i < PX; ++i) {
-          const uint32_t vv = lane_of<pix_t>(own, i);
-          const uint32_t vr = (i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last;
-          atomicAdd(gslot(grad_l1(vr, vv, lane_of<pix_t>(dn, i))), 1u);
+          for (int wd = 0; wd < 4; ++wd) {
+            const uint32_t o = own[wd], dw = dn[wd], nx = wd + 1 < 4 ? own[wd + 1] : right_last;
+#pragma unroll
+            for (int pp = 0; pp < 4; ++pp) {
+              const uint32_t a = pp < 3 ? __builtin_amdgcn_perm(dw, o, 0x0c000c00u | (uint32_t)(pp + 1) | (uint32_t)(4 + pp) << 16)
+                                        : __builtin_amdgcn_perm(dw, nx, 0x0c070c00u);
+              const uint32_t b = __builtin_amdgcn_perm(o, o, 0x0c000c00u | (uint32_t)pp | (uint32_t)pp << 16);
+              atomicAdd(gslot(__builtin_amdgcn_sad_u16(a, b, 0u)), 1u);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < PX; ++i) {
+            const uint32_t vv = lane_of<pix_t>(own, i);
+            const uint32_t vr = (i + 1 < PX) ? lane_of<pix_t>(own, i + 1) : right_last;
+            atomicAdd(gslot(grad_l1(vr, vv, lane_of<pix_t>(dn, i))), 1u);
+          }
         }
         const int e = W - 1 - x;
         if (e < PX) {
