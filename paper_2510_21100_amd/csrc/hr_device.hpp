@@ -1182,7 +1182,7 @@ struct SolveCore {
   alignas(16) float bq[BINS + PAD];                 // levels b of B over (l-1), FP32 (zero padded)
   float lraw[BINS + 4];                             // L' of Eq. (12) on A, before Eq. (15); [n] = 0
   float rn[BINS + 4];                               // R' of Eq. (13) on B, before Eq. (14); [n] = 0
-  double rcum[BINS + 1];                            // running sums of R on B (sweeps without a list)
+  double rcum[BINS + 1];                            // running sums of R by level (sweeps without a list)
   float sd[BINS];                                   // s by level (dense)
   float inv2a[BINS];                                // 1 / (2a) for the rows of A
   alignas(8) float rho[BINS + 4];                   // s_m / d_m by class
@@ -1411,12 +1411,18 @@ __device__ __forceinline__ float table_dot(const float* x, const uint32_t* trow,
   return (a4[0] + a4[1]) + (a4[2] + a4[3]);
 }
 
-// sum over s in [s0, s1) of x[s] rho[index(a, b)] with the class computed as
-// trunc(a * (b / (l-1)) + 1/2) in FP32 (u[s] and v are a and b / (l-1), in
-// either order): exact for every a, b < l at l = 256 and 1024, since the
-// rounded product is within 1.3e-4 of a b / (l-1) and that lies at least
-// 1/(2(l-1)) from a half-integer.  s0 and s1 - s0 multiples of 4; x and u
-// zero-padded.  Same shape as table_dot.
+// Class of a level pair from a (as a float) and b / (l-1) (FP32), in either
+// order: the product rounded to the nearest integer by one fused add of 2^23
+// (the low mantissa bits of the sum are then the integer).  Exact for every
+// a, b < l at l = 256 and 1024: the product of the two floats is within
+// 1.3e-4 of a b / (l-1), which lies at least 1/(2(l-1)) from a half-integer.
+__device__ __forceinline__ uint32_t class_of(float u, float v) {
+  return __float_as_uint(fmaf(u, v, 8388608.f)) - 0x4B000000u;
+}
+
+// sum over s in [s0, s1) of x[s] rho[index(a, b)] with the class from
+// class_of (u[s] and v are a and b / (l-1), in either order).  s0 and
+// s1 - s0 multiples of 4; x and u zero-padded.  Same shape as table_dot.
 __device__ __forceinline__ float class_dot(const float* x, const float* u, float v, const float* rho, int s0,
                                            int s1) {
   float a4[4] = {0.f, 0.f, 0.f, 0.f};
@@ -1429,7 +1435,7 @@ __device__ __forceinline__ float class_dot(const float* x, const float* u, float
     const uint32_t uu[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
     float r[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) r[q] = rho[(int)fmaf(__uint_as_float(uu[q]), v, 0.5f)];
+    for (int q = 0; q < 8; ++q) r[q] = rho[class_of(__uint_as_float(uu[q]), v)];
     __builtin_amdgcn_sched_barrier(0);
     a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
     a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
@@ -1446,7 +1452,7 @@ __device__ __forceinline__ float class_dot(const float* x, const float* u, float
     const uint32_t uu[4] = {u0.x, u0.y, u0.z, u0.w};
     float r[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = rho[(int)fmaf(__uint_as_float(uu[q]), v, 0.5f)];
+    for (int q = 0; q < 4; ++q) r[q] = rho[class_of(__uint_as_float(uu[q]), v)];
     __builtin_amdgcn_sched_barrier(0);
     a4[0] = fmaf(__uint_as_float(x0.x), r[0], a4[0]);
     a4[1] = fmaf(__uint_as_float(x0.y), r[1], a4[1]);
@@ -1780,13 +1786,22 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         // rows of A, each contributing a run of B, summed as a difference of
         // FP64 running sums of R (O(1) per run); only the classes of occupied
         // levels (s_m > 0, i.e. m in A) are needed.  Lanes as in cl: the
-        // rows of a class are dealt round-robin over its lanes, two at a time
-        for (int j = t; j <= nB; j += NT) sm.rcum[j] = j < nB ? (double)sm.rn[j] : 0.0;
+        // rows of a class are dealt round-robin over its lanes.  The running
+        // sums are indexed by level (rcum[b] = sum of R over the levels of B
+        // below b), so a run's level bounds address them directly.
+        for (int b = t; b <= BINS; b += NT) {
+          double v = 0.0;
+          if (b < BINS) {
+            const int j = sm.PB[b];
+            if (sm.PB[b + 1] > j) v = (double)sm.rn[j];
+          }
+          sm.rcum[b] = v;
+        }
         __syncthreads();
-        block_scan<NT, double>(sm.rcum, nB + 1, sm.redd);
-        // Run bounds as in class_run_upper, with the class's two numerators
-        // hoisted; four rows per step, each stage's LDS reads issued together.
-        // An empty run has jlo = jhi and adds an exact zero.
+        block_scan<NT, double>(sm.rcum, BINS + 1, sm.redd);
+        // Run [blo, bhi] of levels as in class_run_upper, with the class's two
+        // numerators hoisted; four rows per step, each stage's LDS reads
+        // issued together.  An empty run (blo > bhi) adds an exact zero.
         double d4[4] = {0.0, 0.0, 0.0, 0.0};
         if (cl.q >= 0) {
           constexpr uint32_t D = BINS - 1;
@@ -1794,7 +1809,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           const float nlo = m ? (float)((2u * m - 1u) * D) : 0.f, nhi = (float)((2u * m + 1u) * D);
           int i = cl.q + cl.k;
           if (sm.A[i] == 0) {  // a = 0 (then i = 0 and m = 0): the whole row
-            d4[0] = (double)sm.lraw[i] * (sm.rcum[nB] - sm.rcum[0]);
+            d4[0] = (double)sm.lraw[i] * (sm.rcum[BINS] - sm.rcum[0]);
             i += g;
           }
           for (; i + 3 * g < nA; i += 4 * g) {
@@ -1805,29 +1820,23 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
               lv[x] = sm.lraw[i + x * g];
             }
             __builtin_amdgcn_sched_barrier(0);
-            int jl[4], jh[4];
+            double rl[4], rh[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
               const uint32_t blo = m ? (uint32_t)(nlo * inv[x]) + 1u : 0u;
               const uint32_t bhi = min((uint32_t)(nhi * inv[x]), D);
-              jl[x] = sm.PB[blo];
-              jh[x] = sm.PB[max(bhi + 1u, blo)];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-            double rl[4], rh[4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              rl[x] = sm.rcum[jl[x]];
-              rh[x] = sm.rcum[jh[x]];
+              rl[x] = sm.rcum[blo];
+              rh[x] = sm.rcum[max(bhi + 1u, blo)];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int x = 0; x < 4; ++x) d4[x] = fma((double)lv[x], rh[x] - rl[x], d4[x]);
           }
           for (; i < nA; i += g) {
-            int jlo, jhi;
-            class_run_upper<BINS>(sm, i, m, jlo, jhi);
-            d4[0] = fma((double)sm.lraw[i], sm.rcum[jhi] - sm.rcum[jlo], d4[0]);
+            const float inv = sm.inv2a[i];
+            const uint32_t blo = m ? (uint32_t)(nlo * inv) + 1u : 0u;
+            const uint32_t bhi = min((uint32_t)(nhi * inv), D);
+            d4[0] = fma((double)sm.lraw[i], sm.rcum[max(bhi + 1u, blo)] - sm.rcum[blo], d4[0]);
           }
         }
         double* part = reinterpret_cast<double*>(sm.spare);  // NT lane partials
