@@ -1462,6 +1462,67 @@ __device__ __forceinline__ float class_dot(const float* x, const float* u, float
   return (a4[0] + a4[1]) + (a4[2] + a4[3]);
 }
 
+// For w = 0..3: out[w] = sum over s in [s0, s1) of x[s] rho[index(a, b)]
+// with the class from class_of (u[s] and v[w] are a and b / (l-1), in either
+// order).  The four sums share each read of x and u.  s0 and s1 - s0
+// multiples of 4; x and u zero-padded.
+__device__ __forceinline__ void class_dot4(const float* x, const float* u, const float (&v)[4], const float* rho,
+                                           int s0, int s1, float (&out)[4]) {
+  float a[4][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};
+  for (int s = s0; s < s1; s += 4) {
+    const v4u x0 = *reinterpret_cast<const v4u*>(x + s);
+    const v4u u0 = *reinterpret_cast<const v4u*>(u + s);
+    const float xx[4] = {__uint_as_float(x0.x), __uint_as_float(x0.y), __uint_as_float(x0.z), __uint_as_float(x0.w)};
+    const float uu[4] = {__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z), __uint_as_float(u0.w)};
+    float r[4][4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[w][q] = rho[class_of(uu[q], v[w])];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[w][q & 1] = fmaf(xx[q], r[w][q], a[w][q & 1]);
+  }
+#pragma unroll
+  for (int w = 0; w < 4; ++w) out[w] = a[w][0] + a[w][1];
+}
+
+// Dense sweep without a class list, first pass: out[o] = sum over the nin
+// inputs s of x[s] rho[index] (u[s], vout[o] as in class_dot4).  The inputs
+// are cut into G slices; lane j of slice k takes the outputs j, j + S,
+// j + 2S, j + 3S (S = ceil(nout / 4)), so the lanes of a wave read the same
+// x and u and gather rho at neighbouring classes.  part[k * 4S + o] gets
+// slice k's sum for output o; sweep_total adds the slices up.
+template <int NT>
+__device__ inline void sweep_part(int nout, int nin, const float* x, const float* u, const float* vout,
+                                  const float* rho, float* part) {
+  const int t = threadIdx.x;
+  const int S = (nout + 3) >> 2, ninp = (nin + 3) & ~3;
+  const int G = min(min(NT / S, 32), ninp >> 2);
+  const int L = ((ninp + G - 1) / G + 3) & ~3;
+  const int k = t / S, j = t - k * S;
+  if (k < G) {
+    const int s0 = k * L, s1 = min(s0 + L, ninp);
+    const float v[4] = {vout[j], vout[j + S], vout[j + 2 * S], vout[j + 3 * S]};
+    float acc[4];
+    class_dot4(x, u, v, rho, s0, max(s0, s1), acc);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) part[k * 4 * S + w * S + j] = acc[w];
+  }
+}
+
+// Second pass: the total of output o, slices in order.
+template <int NT>
+__device__ inline float sweep_total(int o, int nout, int nin, const float* part) {
+  const int S = (nout + 3) >> 2, ninp = (nin + 3) & ~3;
+  const int G = min(min(NT / S, 32), ninp >> 2);
+  float acc = part[o];
+  for (int k = 1; k < G; ++k) acc += part[k * 4 * S + o];
+  return acc;
+}
+
 // Class-major list of the cells (i, j) of A x B whose class has s_m > 0
 // (other classes have rho = 0 and their totals are never used), cut into
 // chunks of exactly C cells (C a multiple of 4; the last chunk of a class
@@ -1673,6 +1734,9 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   const int Gc = nB <= NT ? pow2_floor64(NT / nB) : 1;
   const int Gr = nA <= NT ? pow2_floor64(NT / nA) : 1;
   const int Lc = ((nA + Gc - 1) / Gc + 3) & ~3, Lr = ((nB + Gr - 1) / Gr + 3) & ~3;
+  // without a class list the slice sums of sweep_part go to spare (4 NT floats)
+  float* sweep_buf = reinterpret_cast<float*>(sm.spare);
+  static_assert(LIST || sizeof(sm.spare) >= 4 * NT * sizeof(float), "spare holds the sweep slice sums");
   for (int q = t; q < BINS + PAD; q += NT) {
     if (q >= nA) sm.l2c[q] = 0.f;
     if (q >= nB) sm.wc[q] = 0.f;
@@ -1864,26 +1928,39 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     {
       const float invD = 1.f / (block_read<NT>(sm.redf[0]) + p.beta);
       float qr = 0.f, sr = 0.f;
-      for (int base = 0; base < nB * Gc; base += NT) {
-        if (base + (t & ~63) >= nB * Gc) break;  // whole wave past the outputs
-        const int q = base + t;
-        const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
-        const int s0 = k * Lc;  // a multiple of 4
-        const float r = sm.rc[o], bg = p.beta * sm.gc[o];
-        float acc = 0.f;
-        if constexpr (TAB) {
-          const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
-          acc = table_dot(sm.l2c, trow, sm.rho, s0, s0 + Lc, nAp);
-        } else {
-          acc = class_dot(sm.l2c, sm.af, sm.bq[o], sm.rho, s0, s0 + Lc);
-        }
-        acc = group_sum_last(acc, Gc);
-        if (k == Gc - 1 && q / Gc < nB) {
-          const float rn = fmaf(r, acc, bg) * invD;
+      if constexpr (!LIST) {
+        sweep_part<NT>(nB, nA, sm.l2c, sm.af, sm.bq, sm.rho, sweep_buf);
+        __syncthreads();
+        for (int o = t; o < nB; o += NT) {
+          const float r = sm.rc[o];
+          const float rn = fmaf(r, sweep_total<NT>(o, nB, nA, sweep_buf), p.beta * sm.gc[o]) * invD;
           sm.rn[o] = rn;
           sm.wc[o] = rn * r;
           qr += rn * rn;
           sr += rn;
+        }
+      } else {
+        for (int base = 0; base < nB * Gc; base += NT) {
+          if (base + (t & ~63) >= nB * Gc) break;  // whole wave past the outputs
+          const int q = base + t;
+          const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
+          const int s0 = k * Lc;  // a multiple of 4
+          const float r = sm.rc[o], bg = p.beta * sm.gc[o];
+          float acc = 0.f;
+          if constexpr (TAB) {
+            const uint32_t* trow = reinterpret_cast<const uint32_t*>(tabT + o * nAp);
+            acc = table_dot(sm.l2c, trow, sm.rho, s0, s0 + Lc, nAp);
+          } else {
+            acc = class_dot(sm.l2c, sm.af, sm.bq[o], sm.rho, s0, s0 + Lc);
+          }
+          acc = group_sum_last(acc, Gc);
+          if (k == Gc - 1 && q / Gc < nB) {
+            const float rn = fmaf(r, acc, bg) * invD;
+            sm.rn[o] = rn;
+            sm.wc[o] = rn * r;
+            qr += rn * rn;
+            sr += rn;
+          }
         }
       }
       wave_partial<NT>(qr, sm.redf[1]);
@@ -1894,24 +1971,34 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     {
       const float invD = 1.f / (block_read<NT>(sm.redf[1]) + p.alpha);
       float sl = 0.f;
-      for (int base = 0; base < nA * Gr; base += NT) {
-        if (base + (t & ~63) >= nA * Gr) break;  // whole wave past the outputs
-        const int q = base + t;
-        const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
-        const int s0 = k * Lr;
-        const float lo = sm.lc[o], as = p.alpha * sm.sc[o];
-        float acc = 0.f;
-        if constexpr (TAB) {
-          const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
-          acc = table_dot(sm.wc, trow, sm.rho, s0, s0 + Lr, nBp);
-        } else {
-          acc = class_dot(sm.wc, sm.bq, sm.af[o], sm.rho, s0, s0 + Lr);
-        }
-        acc = group_sum_last(acc, Gr);
-        if (k == Gr - 1 && q / Gr < nA) {
-          const float ln = fmaf(lo, acc, as) * invD;
+      if constexpr (!LIST) {
+        sweep_part<NT>(nA, nB, sm.wc, sm.bq, sm.af, sm.rho, sweep_buf);
+        __syncthreads();
+        for (int o = t; o < nA; o += NT) {
+          const float ln = fmaf(sm.lc[o], sweep_total<NT>(o, nA, nB, sweep_buf), p.alpha * sm.sc[o]) * invD;
           sm.lraw[o] = ln;
           sl += ln;
+        }
+      } else {
+        for (int base = 0; base < nA * Gr; base += NT) {
+          if (base + (t & ~63) >= nA * Gr) break;  // whole wave past the outputs
+          const int q = base + t;
+          const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
+          const int s0 = k * Lr;
+          const float lo = sm.lc[o], as = p.alpha * sm.sc[o];
+          float acc = 0.f;
+          if constexpr (TAB) {
+            const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
+            acc = table_dot(sm.wc, trow, sm.rho, s0, s0 + Lr, nBp);
+          } else {
+            acc = class_dot(sm.wc, sm.bq, sm.af[o], sm.rho, s0, s0 + Lr);
+          }
+          acc = group_sum_last(acc, Gr);
+          if (k == Gr - 1 && q / Gr < nA) {
+            const float ln = fmaf(lo, acc, as) * invD;
+            sm.lraw[o] = ln;
+            sl += ln;
+          }
         }
       }
       wave_partial<NT>(sl, sm.redf[3]);
