@@ -1349,6 +1349,52 @@ __device__ inline ClassLanes class_lanes(int nA, int t) {
   return r;
 }
 
+// Lanes of the class sweep without a list: the levels in groups of CK
+// consecutive classes (group p: classes CK p .. CK p + CK - 1, up to the
+// largest level of A), reached by the rows a >= CK p.  With at most c rows
+// per lane, group p gets ceil(rows_p / c) consecutive lanes; c is the
+// smallest value for which all groups fit in NT lanes.  first: LDS scratch
+// of P + 1 ints.  Every thread of the block calls it.
+template <int BINS, int NT, int CK>
+__device__ ClassLanes group_lanes(SolveCore<BINS, NT>& sm, int* first) {
+  const int t = threadIdx.x, nA = sm.nA;
+  const int P = sm.A[nA - 1] / CK + 1;  // <= BINS / CK <= NT
+  if (t < 64) {
+    int lo = 1, hi = nA;  // c = nA: one lane per group
+    while (lo < hi) {
+      const int c = (lo + hi) >> 1;
+      int n = 0;
+      for (int q = t; q < P; q += 64) n += (nA - sm.PA[CK * q] + c - 1) / c;
+      if (wave_sum(n) <= NT)
+        hi = c;
+      else
+        lo = c + 1;
+    }
+    if (t == 0) sm.redi[0] = lo;
+  }
+  __syncthreads();
+  const int c = sm.redi[0];
+  for (int q = t; q <= P; q += NT) first[q] = q < P ? (nA - sm.PA[CK * q] + c - 1) / c : 0;
+  __syncthreads();
+  block_scan<NT, int32_t>(first, P + 1, sm.redi);
+  ClassLanes r{-1, 0, 1, c};
+  if (t < first[P]) {
+    int a = 0, b = P - 1;  // last group whose first lane is <= t
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (first[mid] <= t)
+        a = mid;
+      else
+        b = mid - 1;
+    }
+    r.q = a;
+    r.k = t - first[a];
+    r.g = first[a + 1] - first[a];
+  }
+  __syncthreads();
+  return r;
+}
+
 // Cell words of a class-list chunk, four at a time.
 template <typename cell_t>
 __device__ __forceinline__ void cells_of(const cell_t* q, uint32_t* e) {
@@ -1758,7 +1804,10 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     sm.lc[nA] = 0.f;
     sm.rc[nB] = 0.f;
   }
-  const ClassLanes cl = LIST ? ClassLanes{-1, 0, 1, 1} : class_lanes<NT>(nA, t);
+  // without a list: classes in groups of CK (see group_lanes)
+  constexpr int CK = 4;
+  ClassLanes cl{-1, 0, 1, 1};
+  if constexpr (!LIST) cl = group_lanes<BINS, NT, CK>(sm, reinterpret_cast<int*>(sm.spare));
   // class list: per round, the first lane of this lane's class in the wave
   // (64: padding chunk) and the class this lane completes (-1: none)
   constexpr int RMAX = SolveCore<BINS, NT>::RMAX;
@@ -1863,54 +1912,77 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
         }
         __syncthreads();
         block_scan<NT, double>(sm.rcum, BINS + 1, sm.redd);
-        // Run [blo, bhi] of levels as in class_run_upper, with the class's two
-        // numerators hoisted; four rows per step, each stage's LDS reads
-        // issued together.  An empty run (blo > bhi) adds an exact zero.
-        double d4[4] = {0.0, 0.0, 0.0, 0.0};
+        // A lane takes CK consecutive classes m0 .. m0 + CK - 1 on its rows:
+        // on row a the runs of the classes are [E(m), E(m + 1)) with
+        // E(m) = floor((2m - 1)(l-1) / 2a) + 1 (capped at l, E(0) = 0), the
+        // lower bound of class_run_upper, so CK + 1 bounds and running-sum
+        // reads give the CK runs.  Classes above a get E = l on both ends, an
+        // exact zero.  Two rows per step, each stage's LDS reads issued
+        // together.
+        double acc[CK];
+#pragma unroll
+        for (int w = 0; w < CK; ++w) acc[w] = 0.0;
         if (cl.q >= 0) {
           constexpr uint32_t D = BINS - 1;
-          const int m = sm.A[cl.q], g = cl.g;
-          const float nlo = m ? (float)((2u * m - 1u) * D) : 0.f, nhi = (float)((2u * m + 1u) * D);
-          int i = cl.q + cl.k;
-          if (sm.A[i] == 0) {  // a = 0 (then i = 0 and m = 0): the whole row
-            d4[0] = (double)sm.lraw[i] * (sm.rcum[BINS] - sm.rcum[0]);
+          const int m0 = CK * cl.q, g = cl.g;
+          float num[CK + 1];  // (2m - 1)(l-1), exact in FP32
+#pragma unroll
+          for (int w = 0; w <= CK; ++w) num[w] = (float)((2 * (m0 + w) - 1) * (int)D);
+          int i = sm.PA[m0] + cl.k;
+          if (i < nA && sm.A[i] == 0) {  // a = 0 (group 0): the whole row is class 0
+            acc[0] = (double)sm.lraw[i] * (sm.rcum[BINS] - sm.rcum[0]);
             i += g;
           }
-          for (; i + 3 * g < nA; i += 4 * g) {
-            float inv[4], lv[4];
+          for (; i + g < nA; i += 2 * g) {
+            float inv[2], lv[2];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
+            for (int x = 0; x < 2; ++x) {
               inv[x] = sm.inv2a[i + x * g];
               lv[x] = sm.lraw[i + x * g];
             }
             __builtin_amdgcn_sched_barrier(0);
-            double rl[4], rh[4];
+            double r[2][CK + 1];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-              const uint32_t blo = m ? (uint32_t)(nlo * inv[x]) + 1u : 0u;
-              const uint32_t bhi = min((uint32_t)(nhi * inv[x]), D);
-              rl[x] = sm.rcum[blo];
-              rh[x] = sm.rcum[max(bhi + 1u, blo)];
-            }
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int w = 0; w <= CK; ++w) {
+                const uint32_t e = (m0 + w) ? min((uint32_t)(num[w] * inv[x]) + 1u, (uint32_t)BINS) : 0u;
+                r[x][w] = sm.rcum[e];
+              }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int x = 0; x < 4; ++x) d4[x] = fma((double)lv[x], rh[x] - rl[x], d4[x]);
+            for (int x = 0; x < 2; ++x) {
+              const double l = (double)lv[x];
+#pragma unroll
+              for (int w = 0; w < CK; ++w) acc[w] = fma(l, r[x][w + 1] - r[x][w], acc[w]);
+            }
           }
-          for (; i < nA; i += g) {
+          if (i < nA) {
             const float inv = sm.inv2a[i];
-            const uint32_t blo = m ? (uint32_t)(nlo * inv) + 1u : 0u;
-            const uint32_t bhi = min((uint32_t)(nhi * inv), D);
-            d4[0] = fma((double)sm.lraw[i], sm.rcum[max(bhi + 1u, blo)] - sm.rcum[blo], d4[0]);
+            const double l = (double)sm.lraw[i];
+            double r[CK + 1];
+#pragma unroll
+            for (int w = 0; w <= CK; ++w) {
+              const uint32_t e = (m0 + w) ? min((uint32_t)(num[w] * inv) + 1u, (uint32_t)BINS) : 0u;
+              r[w] = sm.rcum[e];
+            }
+#pragma unroll
+            for (int w = 0; w < CK; ++w) acc[w] = fma(l, r[w + 1] - r[w], acc[w]);
           }
         }
-        double* part = reinterpret_cast<double*>(sm.spare);  // NT lane partials
-        part[t] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+        double* part = reinterpret_cast<double*>(sm.spare);  // CK x NT lane partials
+        static_assert(LIST || sizeof(sm.spare) >= CK * NT * sizeof(double), "spare holds the class partials");
+#pragma unroll
+        for (int w = 0; w < CK; ++w) part[w * NT + t] = acc[w];
         __syncthreads();
         if (cl.q >= 0 && cl.k == 0) {
-          double d = 0.0;
-          for (int x = 0; x < cl.g; ++x) d += part[t + x];
-          const int m = sm.A[cl.q];
-          sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d) : 0.f;
+          for (int w = 0; w < CK; ++w) {
+            const int m = CK * cl.q + w;
+            if (m >= BINS || sm.PA[m + 1] == sm.PA[m]) continue;  // only the classes of A
+            double d = 0.0;
+            for (int x = 0; x < cl.g; ++x) d += part[w * NT + t + x];
+            sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d) : 0.f;
+          }
         }
       }
       float ql = 0.f;
