@@ -241,7 +241,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the images of a batch are independent and this build "
+        print("bench.py runs on exactly one GPU: the images of a batch are independent and the bench "
               "measures one GPU's share; use --gpus 1", file=sys.stderr)
         raise SystemExit(2)
 

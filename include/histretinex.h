@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   HR_OK = 0,
   HR_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad parameter value      */
-  HR_ERR_UNSUPPORTED = 2, /* valid but outside what this build implements    */
+  HR_ERR_UNSUPPORTED = 2, /* valid but outside what the library implements   */
   HR_ERR_WORKSPACE = 3,   /* workspace too small for the request              */
   HR_ERR_DEVICE = 4       /* a HIP runtime call failed; see hr_last_error()   */
 } hr_status;
