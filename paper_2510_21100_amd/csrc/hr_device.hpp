@@ -376,6 +376,10 @@ struct HistSmem {
   static constexpr int BINS = Cfg<BITS>::BINS;
   static constexpr int REP = BITS == 8 ? (NT >= 512 ? 16 : 4) : (NT >= 512 ? 4 : 1);
   static constexpr int STRIDE = REP;
+  // the value histogram of 8-bit pixels in the split kernel: 32 copies (a
+  // dark image puts most lanes of a wave on a few levels)
+  static constexpr int REPS = (BITS == 8 && NT >= 1024) ? 32 : REP;
+  static constexpr int STRIDES = REPS;
   // 1024-thread workgroups split into a loading and a gradient half (see
   // HistTileSplit), whose steps are STEPH pixels and lie up to
   // 1 + ceil((W+1)/STEPH) steps apart; smaller ones alternate the two phases
@@ -391,7 +395,7 @@ struct HistSmem {
   // lane, hgs[level * 64 + lane] (measured faster there; slower with the 16
   // copies of 8-bit pixels, where the address select costs more than it saves).
   static constexpr int GSMALL = (NT >= 1024 && BITS == 10) ? 32 : 0;
-  uint32_t hs[BINS * STRIDE];
+  uint32_t hs[BINS * STRIDES];
   uint32_t hg[(2 * BINS - 1) * STRIDE];
   uint32_t hgs[GSMALL > 0 ? GSMALL * 64 : 4];
   alignas(16) uint32_t ring[RING_BYTES / 4 + 16];  // + 64-byte mirror of the start: no wrap on reads
@@ -696,7 +700,7 @@ struct HistTileSplit {
   __device__ HistTileSplit(const ImgDesc& d_, int64_t p0, int64_t p1, SM& sm_)
       : d(d_), sm(sm_), P0(p0), P1(p1), N(d_.npix), E(min(p1 + (int64_t)d_.W, d_.npix)), W(d_.W),
         tt(threadIdx.x & (NH - 1)), step_mod_w(STEP % d_.W), producer(threadIdx.x < NH),
-        hs(sm_.hs + (threadIdx.x & (REP - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))),
+        hs(sm_.hs + (threadIdx.x & (SM::REPS - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))),
         hgl(sm_.hgs + (threadIdx.x & 63)) {
     x = (int)((P0 + (int64_t)tt * PX) % W);
   }
@@ -738,11 +742,11 @@ struct HistTileSplit {
     const int64_t nh = P1 - p;
     if (nh >= PX) {
 #pragma unroll
-      for (int i = 0; i < PX; ++i) atomicAdd(&hs[v[i] * SD], 1u);
+      for (int i = 0; i < PX; ++i) atomicAdd(&hs[v[i] * SM::STRIDES], 1u);
     } else {
 #pragma unroll
       for (int i = 0; i < PX; ++i)
-        if (i < nh) atomicAdd(&hs[v[i] * SD], 1u);
+        if (i < nh) atomicAdd(&hs[v[i] * SM::STRIDES], 1u);
     }
   }
 
@@ -909,7 +913,7 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
   using SM = HistSmem<BITS, NT>;
   constexpr int BINS = Cfg<BITS>::BINS, REP = SM::REP, SD = SM::STRIDE;
   const int t = threadIdx.x;
-  for (int i = t; i < BINS * SD; i += NT) sm.hs[i] = 0;
+  for (int i = t; i < BINS * SM::STRIDES; i += NT) sm.hs[i] = 0;
   for (int i = t; i < (2 * BINS - 1) * SD; i += NT) sm.hg[i] = 0;
   for (int i = t; i < SM::GSMALL * 64; i += NT) sm.hgs[i] = 0;
   if (t == 0) sm.clamped = 0;
@@ -929,7 +933,7 @@ __device__ void hist_tile(const ImgDesc& d, int64_t P0, int64_t P1, HistSmem<BIT
   for (int k = t; k < BINS; k += NT) {
     uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < REP; ++r) s += sm.hs[k * SD + r];
+    for (int r = 0; r < SM::REPS; ++r) s += sm.hs[k * SM::STRIDES + r];
     if (s) __hip_atomic_fetch_add(to_global(g_hs) + k, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   for (int k = t; k < 2 * BINS - 1; k += NT) {
