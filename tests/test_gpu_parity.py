@@ -131,6 +131,32 @@ def test_solve_degenerate(H, name):
     assert max(e) <= 10 * REL_TOL
 
 
+@pytest.mark.parametrize("bits", [8, 10])
+@pytest.mark.parametrize("name", sorted(edge_images(10)))
+def test_solve_edge_images(H, bits, name):
+    # every edge image at both level counts, 50 passes: one occupied level
+    # (black, white, constant), two levels, single rows and columns
+    img = edge_images(bits)[name]
+    e = _solve_case(H, img, O.Params(bins=1 << bits, iters=50))
+    assert max(e) <= 10 * REL_TOL
+
+
+def test_solve_parity_10bit_all_levels(H):
+    # uniform random 10-bit pixels: V on ~950 levels and ~850 gradient levels,
+    # the most classes and the widest sweeps at 1024 levels
+    img = np.random.default_rng(11).integers(0, 1024, size=(192, 256, 3), dtype=np.uint16)
+    e = _solve_case(H, img, O.Params(bins=1024, iters=50))
+    print("rel err illum %.2e refl %.2e target %.2e" % e)
+    assert e[0] <= REL_TOL and e[1] <= REL_TOL and e[2] <= 10 * REL_TOL
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+def test_solve_few_iterations_10bit(H, iters):
+    img = cfg_image(4, 90, 120, bits=10)
+    e = _solve_case(H, img, O.Params(bins=1024, iters=iters))
+    assert max(e[:2]) <= REL_TOL
+
+
 @pytest.mark.parametrize("bits,shape", [(8, (256, 256)), (8, (664, 1000)), (10, (200, 300))])
 def test_match_given_target(H, bits, shape):
     """LUT and remap from the same FP32 target as the oracle: the LUT must be
