@@ -1194,7 +1194,7 @@ struct SolveCore {
   int32_t off[BINS + 1];                            // first chunk of class m
   int32_t csz[BINS];                                // cells of class m
   int32_t PA[BINS + 1], PB[BINS + 1];               // occupied levels below a / b
-  int32_t lane_cells[NT];                           // list build: cells of each lane's rows
+  int32_t lane_cells[NT];                           // list build: cells of each lane's rows, then their rank
   int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
   float redf[4][NT / 64];
   uint64_t redu[NT / 64];
@@ -1616,6 +1616,7 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
     if (cl.k == cl.g - 1) sm.csz[mcls] = before + mine;
   }
   __syncthreads();
+  sm.lane_cells[t] = before;  // rank of the lane's first cell in its class (read after the layout's barrier)
   int mx = 0, tot = 0;
   for (int m = t; m < BINS; m += NT) {
     const int c = sm.csz[m];
@@ -1707,18 +1708,46 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
     const int s0 = m >= 0 ? max(0, min(C, sm.csz[m] - (u - sm.off[m]) * C)) : 0;
     for (int s = s0; s < C; ++s) cells[(size_t)u * CS + s] = zero_cell;
   }
-  // this lane's cells from rank `before` on, along its rows' runs
-  if (mine > 0) {
-    int u = sm.off[mcls] + before / C, s = before - (before / C) * C;
-    for (int i = i0; i < i1; ++i) {
-      int jlo, jhi;
-      class_run_upper<BINS>(sm, i, mcls, jlo, jhi);
-      for (int j = jlo; j < jhi; ++j) {
-        cells[(size_t)u * CS + s] = (cell_t)(i | (j << SH));
-        if (++s == C) {
-          s = 0;
-          ++u;
+  // the cells, one lane per chunk (C cells each): the chunk's first cell has
+  // rank (u - off[m]) C in its class; the class's lanes of the count above
+  // (consecutive, c rows each from row q) hold the ranks of their first
+  // cells, so a binary search names the lane and at most c rows are skipped
+  // from its first row before the chunk's cells follow the rows' runs
+  {
+    const int c = cl.c;
+    const int total = lanes_upto(nA, c);
+    for (int r = 0; r < R; ++r) {
+      const int u = r * NT + t;
+      const int m = sm.chunk_cls[u];
+      if (m < 0) continue;
+      const int q = sm.PA[m];  // m is a level of A: its class index
+      const int f = total - lanes_upto(nA - q, c), g = (nA - q + c - 1) / c;
+      const int rank0 = (u - sm.off[m]) * C;
+      int lo = 0, hi = g - 1;  // last lane whose first rank is <= rank0
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sm.lane_cells[f + mid] <= rank0)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      int skip = rank0 - sm.lane_cells[f + lo];
+      int i = q + lo * c, jlo = 0, jhi = 0;
+      for (;; ++i) {  // the row holding rank rank0 (it exists: rank0 < csz[m])
+        class_run_upper<BINS>(sm, i, m, jlo, jhi);
+        if (skip < jhi - jlo) break;
+        skip -= jhi - jlo;
+      }
+      int j = jlo + skip;
+      const int n = min(C, sm.csz[m] - rank0);
+      for (int k = 0; k < n; ++k) {
+        while (j == jhi) {  // next row with cells of class m
+          ++i;
+          class_run_upper<BINS>(sm, i, m, jlo, jhi);
+          j = jlo;
         }
+        cells[(size_t)u * CS + k] = (cell_t)(i | (j << SH));
+        ++j;
       }
     }
   }
