@@ -53,8 +53,6 @@ __device__ inline uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
   return max(max(a, b), c);
 }
 
-__device__ inline uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
-
 // Cross-workgroup hand-off.  The release and acquire fences at agent scope
 // write back / invalidate the whole L2 of the XCD, so one wave issues them on
 // behalf of its workgroup: every wave first drains its own memory operations
@@ -1790,9 +1788,11 @@ __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, 
   }
 }
 
-// The Alg. 1 loop.  LIST: class totals from the class list (else per-class
-// gathers over row runs); CELLS_LDS / TAB: where the list and the class
-// tables live, so that every access compiles to its address space.
+// The Alg. 1 loop.  LIST: class totals from the class list and sweeps over
+// power-of-two lane groups per output (else class totals from running sums
+// over row runs, four classes per lane, and sweeps with four outputs per lane
+// over input slices); CELLS_LDS / TAB: where the list and the class tables
+// live, so that every access compiles to its address space.
 template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
 __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
                         const SolveParams& p, float* ckpt) {
@@ -1808,8 +1808,8 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   const uint8_t* tab = class_table(sm);
   const uint8_t* tabT = tab + nA * sm.nBp;
   const int nAp = sm.nAp, nBp = sm.nBp;
-  // dense sweeps: output o split over G lanes (a power of two); slice k covers
-  // L inputs (a multiple of 4), zero-padded past the end
+  // dense sweeps with a class list: output o split over G lanes (a power of
+  // two); slice k covers L inputs (a multiple of 4), zero-padded past the end
   const int Gc = nB <= NT ? pow2_floor64(NT / nB) : 1;
   const int Gr = nA <= NT ? pow2_floor64(NT / nA) : 1;
   const int Lc = ((nA + Gc - 1) / Gc + 3) & ~3, Lr = ((nB + Gr - 1) / Gr + 3) & ~3;
