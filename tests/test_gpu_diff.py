@@ -145,9 +145,8 @@ def test_solve_vjp_matches_the_reference(H):
     ws.close()
 
 
-def test_enhancement_loss_end_to_end(H):
+def _loss_case(H, cases):
     H, diff = H
-    cases = _images(SHAPES[:2])
     n = len(cases)
     imgs = [to_gpu(img) for img, _ in cases]
     tims = [torch.from_numpy(t).cuda() for _, t in cases]
@@ -171,6 +170,16 @@ def test_enhancement_loss_end_to_end(H):
     assert abs(float(loss.detach()) - ref_loss) <= 1e-4 * ref_loss
     assert abs(float(alpha.grad) - ref_da) <= GRAD_REL * abs(ref_da), (float(alpha.grad), ref_da)
     assert abs(float(beta.grad) - ref_db) <= GRAD_REL * abs(ref_db), (float(beta.grad), ref_db)
+
+
+def test_enhancement_loss_end_to_end(H):
+    _loss_case(H, _images(SHAPES[:2]))
+
+
+def test_enhancement_loss_full_size(H):
+    # the bench's differentiated workload: 32 images of 1000x664, K = 30,
+    # checkpoints every 5; every image against the FP64 reference
+    _loss_case(H, _images([(664, 1000)] * 32))
 
 
 def test_diff_calls_validate(H):
