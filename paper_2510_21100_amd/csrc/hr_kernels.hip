@@ -149,10 +149,8 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
   for (int k = threadIdx.x; k < 3 * BINS; k += NT_BATCH) {
     uint32_t v = 0;
 #pragma unroll
-    for (int q = 0; q < ImageState::NSLOT; ++q) {
+    for (int q = 0; q < ImageState::NSLOT; ++q)
       v += __hip_atomic_load(to_global(s->slot(BINS, q)) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s->slot(BINS, q)[k] = 0u;  // zero for the next call (no other workgroup touches them now)
-    }
     if (k < BINS) hs[k] = v;
     else if (k < 3 * BINS - 1) graw[k - BINS] = v;
   }
@@ -189,6 +187,17 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
     const uint32_t pos = atomicAdd(&hdr->nready, 1u);
     __hip_atomic_store(to_global(&ctr[pos].fifo), (uint32_t)i + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
+  // zero the partial slots for the next call (no other workgroup touches them
+  // now; their loads above have returned), after the image is published: the
+  // stores are written back to memory with a release like the publication's,
+  // where the next call's histogram atomics will find them
+  for (int k = threadIdx.x; k < 3 * BINS; k += NT_BATCH) {
+#pragma unroll
+    for (int q = 0; q < ImageState::NSLOT; ++q) s->slot(BINS, q)[k] = 0u;
+  }
+  drain_memory();
+  __syncthreads();
+  if (threadIdx.x == 0) fence_release_agent();
 }
 
 // image owning histogram item `it` (tile0 ascending over the descriptor table)
