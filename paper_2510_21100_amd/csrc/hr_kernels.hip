@@ -144,27 +144,42 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
   constexpr int BINS = Cfg<BITS>::BINS;
   ImageState* s = state_of(st, st_words, i);
   uint32_t* hs = s->hs();
-  uint32_t* graw = s->graw(BINS);
-  uint32_t* hg = s->hg(BINS);
+  // The summed histograms are handed to the rebin and the solver's setup in
+  // LDS (the solver's spare area, unused until its class list), so no wait
+  // for global stores sits on the image's critical path; the value histogram
+  // also goes to the state for the LUT.
+  uint32_t* lhs = reinterpret_cast<uint32_t*>(sm.solve.spare);  // [BINS]
+  uint32_t* lgraw = lhs + BINS;                                  // [2 BINS - 1]
+  uint32_t* lhg = lhs + 3 * BINS;                                // [BINS]
+  static_assert(sizeof(sm.solve.spare) >= 4 * BINS * sizeof(uint32_t), "spare holds the histograms");
+  uint32_t gm = 0;
   for (int k = threadIdx.x; k < 3 * BINS; k += NT_BATCH) {
     uint32_t v = 0;
 #pragma unroll
     for (int q = 0; q < ImageState::NSLOT; ++q)
       v += __hip_atomic_load(to_global(s->slot(BINS, q)) + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (k < BINS) hs[k] = v;
-    else if (k < 3 * BINS - 1) graw[k - BINS] = v;
+    if (k < BINS) {
+      lhs[k] = v;
+      hs[k] = v;
+      lhg[k] = 0;
+    } else if (k < 3 * BINS - 1) {
+      lgraw[k - BINS] = v;
+      if (v) gm = max(gm, (uint32_t)(k - BINS));
+    }
   }
-  drain_memory();
-  __syncthreads();
-  rebin_gradient<BINS, NT_BATCH>(graw, hg, reinterpret_cast<uint32_t*>(&sm), red);
-  drain_memory();
+  // rebin of the gradient histogram (as rebin_gradient), in LDS
+  const uint32_t gmax = block_max<NT_BATCH>(gm, red);
+  for (int j = threadIdx.x; j <= (int)gmax; j += NT_BATCH) {
+    const uint32_t c = lgraw[j];
+    if (c) atomicAdd(&lhg[gmax ? (uint32_t)((2ull * (BINS - 1) * j + gmax) / (2ull * gmax)) : 0u], c);
+  }
   __syncthreads();
   const int64_t npix = desc[i].npix;
   const int slot = desc[i].slot;
   const BatchOut out = hdr->out;
   float* tgt = s->target(BINS);
   solve_image<BINS, NT_BATCH, BatchBudget<BITS>::value>(
-      hs, hg, npix, hdr->params, sm.solve,
+      lhs, lhg, npix, hdr->params, sm.solve,
       reinterpret_cast<typename CellT<BINS>::type*>(lists_base + (int64_t)i * lists_stride),
       lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),
       out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
