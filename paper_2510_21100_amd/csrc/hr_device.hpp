@@ -2189,13 +2189,25 @@ __device__ uint64_t solve_setup(const uint32_t* hS, const uint32_t* hG, int64_t 
 // LDS.  Writes illum/refl/target (counts, dense over the l levels) when
 // non-null, and with ckpt non-null and p.ckpt_every > 0 the dense (L, R) of
 // t = 0, every, 2 every, ... (2 l floats each, see write_state).
-template <int BINS, int NT, int BUDGET>
+template <int BINS, int NT, int BUDGET, bool MAY_BE_EMPTY = true>
 __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
                             SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
                             float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr) {
   const int t = threadIdx.x;
   const uint64_t Ns = solve_setup<BINS, NT>(hS, hG, npix, sm, flags);
   const int nA = sm.nA, nB = sm.nB;
+  // no mass at all (flagged by the setup; histograms of an image always have
+  // mass, MAY_BE_EMPTY = false): zero outputs
+  if (MAY_BE_EMPTY && (nA == 0 || nB == 0)) {
+    for (int k = t; k < BINS; k += NT) {
+      if (target) target[k] = 0.f;
+      if (illum) illum[k] = 0.f;
+      if (refl) refl[k] = 0.f;
+    }
+    if (ckpt && p.ckpt_every > 0)
+      for (int64_t k = t; k < (int64_t)(p.iters / p.ckpt_every + 1) * 2 * BINS; k += NT) ckpt[k] = 0.f;
+    return;
+  }
   if constexpr (BINS == 256) {
     build_class_list<BINS, NT, BUDGET>(sm, gcells, gcap);
     if (!sm.use_list)

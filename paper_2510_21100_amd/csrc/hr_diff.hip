@@ -430,6 +430,13 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
   const int img = blockIdx.x, t = threadIdx.x;
   const uint64_t N = solve_setup<BINS, NT_VJP>(hv + (size_t)img * BINS, hg + (size_t)img * BINS, -1, sm, flags);
   const int nA = sm.nA, nB = sm.nB, E = p.ckpt_every;
+  if (nA == 0 || nB == 0) {  // no mass (flagged by the setup): h~ is 0 and so is its gradient
+    if (t == 0) {
+      dalpha[img] = 0.0;
+      dbeta[img] = 0.0;
+    }
+    return;
+  }
   const float* ck = ckpt + (size_t)img * ncp * 2 * BINS;
   if (t < nA) {
     const int a = sm.A[t];

@@ -178,7 +178,7 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
   const int slot = desc[i].slot;
   const BatchOut out = hdr->out;
   float* tgt = s->target(BINS);
-  solve_image<BINS, NT_BATCH, BatchBudget<BITS>::value>(
+  solve_image<BINS, NT_BATCH, BatchBudget<BITS>::value, false>(
       lhs, lhg, npix, hdr->params, sm.solve,
       reinterpret_cast<typename CellT<BINS>::type*>(lists_base + (int64_t)i * lists_stride),
       lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),

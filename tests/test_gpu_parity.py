@@ -208,3 +208,42 @@ def test_end_to_end_plain(H, cfg, shape, bits):
     ties = lut_contract(to_np(ex["lut"]), ref)
     frac = pixel_contract(to_np(out), ref["out"])
     print(f"near-tie levels {ties}, pixels off by one {frac:.2e}")
+
+
+@pytest.mark.parametrize("bits", [8, 10])
+def test_solve_empty_histograms_flagged(H, bits):
+    # histograms without mass (a caller error the host cannot see): the mass
+    # flag is set and every output is zero
+    from paper_2510_21100_amd import _lib
+    bins = 1 << bits
+    ws = H.Workspace(max_images=1, max_bins=bins)
+    ws.flags(clear=True)
+    z = torch.zeros(bins, dtype=torch.int32, device="cuda")
+    illum, refl, target = H.solve(z, z.clone(), 100, H.Params(bins=bins, iters=50), ws)
+    torch.cuda.synchronize()
+    assert ws.flags(clear=True) & _lib.HR_FLAG_HIST_MASS
+    for x in (illum, refl, target):
+        assert not torch.any(x != 0)
+    ws.close()
+
+
+def test_solve_mass_mismatch_flagged(H):
+    # npix different from the histogram mass: flagged; the solve itself uses
+    # the histograms as given
+    from paper_2510_21100_amd import _lib
+    img = cfg_image(2, 64, 80)
+    hS, graw, gmax, hG = oracle_hists(img, 256)
+    N = int(hS.sum())
+    hv = torch.from_numpy(hS.astype(np.int32)).cuda()
+    hg = torch.from_numpy(hG.astype(np.int32)).cuda()
+    ws = H.Workspace(max_images=1, max_bins=256)
+    ws.flags(clear=True)
+    ref = H.solve(hv, hg, N, H.Params(bins=256), ws)
+    torch.cuda.synchronize()
+    assert not ws.flags(clear=True) & _lib.HR_FLAG_HIST_MASS
+    got = H.solve(hv, hg, N + 1, H.Params(bins=256), ws)
+    torch.cuda.synchronize()
+    assert ws.flags(clear=True) & _lib.HR_FLAG_HIST_MASS
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)
+    ws.close()
