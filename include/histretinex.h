@@ -142,7 +142,11 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
  * The updates are Eq. (13) for R then Eq. (12) for L (with the weights K of
  * Eq. (11) multiplying, as in the stationarity conditions of Eq. (10)), then
  * the rescalings of Eqs. (15), (14), starting from R = H_C(grad S) and
- * L = H_C(S).  Runs in FP32 on one workgroup. */
+ * L = H_C(S).  Runs in FP32 on one workgroup.  The histograms are checked on
+ * the device: a mass of hist_v other than npix, or of hist_grad other than
+ * that of hist_v, sets HR_FLAG_HIST_MASS (read with hr_get_flags) and the
+ * histograms are used as given; histograms without any mass give zero
+ * outputs. */
 hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix,
                    const hr_params* p, float* illum, float* refl, float* target, hr_workspace* ws,
                    void* stream);
