@@ -1,0 +1,88 @@
+"""The GPU solver never evaluates index(a, b) of Eq. (10) with integer
+division in its hot loops: it uses FP32 shortcuts.  These tests emulate those
+shortcuts bit for bit in numpy and compare them, for every level pair, with
+the exact integer forms:
+
+  * class of a cell in the dense sweeps: the product a * float32(b / (l-1)),
+    plus 2^23, rounded once to FP32 (one fused multiply-add), whose low
+    mantissa bits are then the class;
+  * the run of reflectance levels of class m on illumination row a (class
+    list, 1024-level class totals, reverse pass): the FP32 product
+    float32((2m +- 1)(l-1)) * float32(1 / (2a)), truncated, gives the lower
+    bound E(m) = floor((2m-1)(l-1) / 2a) + 1 (capped at l) and the upper
+    bound floor((2m+1)(l-1) / 2a) (capped at l-1).
+
+The exact references are integer arithmetic only (no oracle code).
+"""
+
+import numpy as np
+import pytest
+
+
+def _round_half_even_exact(x: np.ndarray) -> np.ndarray:
+    # x holds exact values (products of small integers and float32 values,
+    # at most 34 significant bits, exact in float64)
+    return np.rint(x).astype(np.int64)
+
+
+@pytest.mark.parametrize("levels", [256, 1024])
+def test_dense_sweep_class_rounding_is_exact(levels):
+    D = levels - 1
+    a = np.arange(levels, dtype=np.float32)
+    bq = np.arange(levels, dtype=np.float32) / np.float32(D)  # IEEE FP32 division
+    assert bq.dtype == np.float32
+    # fmaf(a, bq, 2^23): the exact product plus 2^23, rounded once to FP32.
+    # Sums in [2^23, 2^24) are spaced 1 apart in FP32, so that rounding is
+    # round-half-even of the exact product.  The product of a 10-bit integer
+    # and a float32 is exact in float64.
+    prod = np.multiply.outer(a.astype(np.float64), bq.astype(np.float64))
+    assert np.all(prod < 2.0 ** 23)
+    cls = _round_half_even_exact(prod)
+    A = np.arange(levels, dtype=np.int64)[:, None]
+    B = np.arange(levels, dtype=np.int64)[None, :]
+    exact = (2 * A * B + D) // (2 * D)
+    assert np.array_equal(cls, exact)
+    # the FP32 product is never within 1e-4 of a rounding boundary (the
+    # exact a b / (l-1) lies at least 1 / (2 (l-1)) from one)
+    dist = np.abs(prod - np.floor(prod) - 0.5)
+    assert dist.min() > 1e-4
+
+
+def _fp32_run_bounds(levels: int, a: int, m: np.ndarray):
+    """(E(m), upper(m)) as the device computes them for row a >= 1."""
+    D = levels - 1
+    inv = np.float32(1.0) / np.float32(2 * a)  # IEEE FP32 division
+    lo_num = ((2 * m - 1) * D).astype(np.float32)  # exact: below 2^24
+    hi_num = ((2 * m + 1) * D).astype(np.float32)
+    lo = np.floor((lo_num * inv).astype(np.float64)).astype(np.int64)  # truncation of a positive float
+    hi = np.floor((hi_num * inv).astype(np.float64)).astype(np.int64)
+    E = np.where(m == 0, 0, np.minimum(lo + 1, levels))
+    upper = np.minimum(hi, levels - 1)
+    return E, upper
+
+
+@pytest.mark.parametrize("levels", [256, 1024])
+def test_class_run_bounds_are_exact(levels):
+    D = levels - 1
+    for a in range(1, levels):
+        m = np.arange(0, min(a + 6, levels + 1), dtype=np.int64)
+        E, upper = _fp32_run_bounds(levels, a, m)
+        E_exact = np.where(m == 0, 0, np.minimum(((2 * m - 1) * D) // (2 * a) + 1, levels))
+        up_exact = np.minimum(((2 * m + 1) * D) // (2 * a), levels - 1)
+        assert np.array_equal(E, E_exact), a
+        mm = m[m <= a]
+        assert np.array_equal(upper[: mm.size], up_exact[: mm.size]), a
+        # classes above a: the run is empty at both ends (E = l)
+        assert np.all(E[m > a] == levels), a
+
+
+@pytest.mark.parametrize("levels", [256, 1024])
+def test_run_bounds_reproduce_the_class_map(levels):
+    """Rows cut into class runs by E(m) give back index(a, b) for every b."""
+    D = levels - 1
+    b = np.arange(levels, dtype=np.int64)
+    for a in range(1, levels, 7 if levels == 1024 else 1):
+        m = np.arange(0, a + 2, dtype=np.int64)
+        E, _ = _fp32_run_bounds(levels, a, m)
+        cls = np.searchsorted(E, b, side="right") - 1
+        assert np.array_equal(cls, (2 * a * b + D) // (2 * D)), a
