@@ -50,6 +50,12 @@ def _image(img: torch.Tensor) -> HrImage:
     return HrImage(img.data_ptr(), img.shape[1], img.shape[0], img.stride(0) * img.element_size())
 
 
+def _on_gpu(t: torch.Tensor, what: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be on the GPU")
+    return t
+
+
 def _stream() -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -90,12 +96,12 @@ _default_ws: dict = {}
 
 def workspace(max_images: int = 1, max_bins: int = 1024) -> Workspace:
     """A process-wide workspace for the current device with room for at least
-    ``max_images`` images."""
+    ``max_images`` images.  A smaller one it replaces is only dropped from the
+    cache: whoever still holds it (a pending backward, say) keeps it alive, and
+    it is freed with its last reference."""
     dev = torch.cuda.current_device()
     ws = _default_ws.get(dev)
     if ws is None or ws.max_images < max_images or ws.max_bins < max_bins:
-        if ws is not None:
-            ws.close()
         ws = Workspace(max(max_images, 1), max(max_bins, 1024))
         _default_ws[dev] = ws
     return ws
@@ -143,6 +149,8 @@ def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Para
         raise ValueError("histograms must have params.bins entries")
     if hist_v.dtype != torch.int32 or hist_grad.dtype != torch.int32:
         raise TypeError("histograms must be int32 tensors")
+    _on_gpu(hist_v, "hist_v")
+    _on_gpu(hist_grad, "hist_grad")
     dev = hist_v.device
     illum = torch.empty(bins, dtype=torch.float32, device=dev)
     refl = torch.empty(bins, dtype=torch.float32, device=dev)
@@ -163,6 +171,8 @@ def match(img: torch.Tensor, hist_v: torch.Tensor, target: torch.Tensor, out: to
         raise ValueError("histograms must have 2^bits entries")
     if target.dtype != torch.float32:
         raise TypeError("target must be float32")
+    _on_gpu(hist_v, "hist_v")
+    _on_gpu(target, "target")
     if out is None:
         out = torch.empty_like(img)
     if out.shape != img.shape or out.dtype != img.dtype:
@@ -205,9 +215,15 @@ def enhance_batch(imgs: Sequence[torch.Tensor], params: Params | None = None,
     bins = 1 << bits
     params = params or Params(bins=bins)
     ws = ws or workspace(max_images=n)
+    arr_in = (HrImage * n)(*[_image(x) for x in imgs])
     if outs is None:
         outs = [torch.empty_like(x) for x in imgs]
-    arr_in = (HrImage * n)(*[_image(x) for x in imgs])
+    if len(outs) != n:
+        raise ValueError("one output per image")
+    for x, o in zip(imgs, outs):
+        _image(o)  # on the GPU, interleaved RGB rows
+        if o.shape != x.shape or o.dtype != x.dtype:
+            raise ValueError("each output must match its image's shape and dtype")
     arr_out = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
     arr_stride = (C.c_int64 * n)(*[o.stride(0) * o.element_size() for o in outs])
     ex = None

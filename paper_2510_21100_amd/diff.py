@@ -104,6 +104,8 @@ def enhancement_loss(images: Sequence[torch.Tensor], target_imgs: Sequence[torch
     for x, t in zip(images, target_imgs):
         if t.dtype != torch.float32 or tuple(t.shape) != tuple(x.shape) or not t.is_contiguous():
             raise ValueError("target images must be contiguous float32 tensors of the image's shape")
+        if not (x.is_cuda and t.is_cuda):
+            raise ValueError("images and target images must be on the GPU")
     ws = ws or api.workspace(max_images=len(images))
     hv, hg = histograms(images, ws)
     target = TargetFn.apply(alpha, beta, hv, hg, iters, gamma, ckpt_every, ws)

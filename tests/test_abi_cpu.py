@@ -153,3 +153,29 @@ def test_workspace_calls_reject_null(L):
     out = C.c_void_p()
     assert L.lib.hr_workspace_create(0, 256, C.byref(out)) == L.HR_ERR_INVALID_ARG
     assert L.lib.hr_workspace_create(4, 512, C.byref(out)) == L.HR_ERR_UNSUPPORTED
+
+
+def test_default_workspace_replacement_keeps_the_old_one_alive(L, monkeypatch):
+    """workspace() grows the cached default workspace by replacing it; a
+    holder of the old one (a pending backward) must still find it open."""
+    from paper_2510_21100_amd import api
+
+    closed = []
+
+    class FakeWorkspace:
+        def __init__(self, max_images=1, max_bins=1024):
+            self.max_images, self.max_bins, self.handle = max_images, max_bins, object()
+
+        def close(self):
+            closed.append(self)
+            self.handle = None
+
+    monkeypatch.setattr(api, "Workspace", FakeWorkspace)
+    monkeypatch.setattr(api, "_default_ws", {})
+    monkeypatch.setattr(api.torch.cuda, "current_device", lambda: 0)
+    small = api.workspace(max_images=2)
+    assert api.workspace(max_images=1) is small
+    big = api.workspace(max_images=8)
+    assert big is not small and big.max_images == 8
+    assert small.handle is not None and not closed
+    assert api.workspace(max_images=3) is big

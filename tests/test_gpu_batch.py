@@ -136,66 +136,25 @@ def test_clamped_10bit_values_flag(H):
     ws.close()
 
 
-def test_full_size_ragged_batch_sampled(H):
-    """The benchmark's 64-image ragged batch: every image's value channel after
-    remap equals its LUT (exact property at any size), and three sampled
-    images match the oracle in full."""
-    shapes = make_batch_shapes(config_seed(3, 1, 0), 64)
-    n = len(shapes)
-    rng = np.random.default_rng(2510211003)
-    ceils = rng.uniform(0.03, 0.4, size=n)
-    sample = {0, 31, 63}
-    gimgs, kept = [], {}
-    for i, (h, w) in enumerate(shapes):
-        img = make_image(config_seed(3, n, i), h, w, ceil=float(ceils[i]))
-        if i in sample:
-            kept[i] = img
-        gimgs.append(to_gpu(img))
-    outs, ex = H.enhance_batch(gimgs, H.Params(bins=256), extras=True)
-    torch.cuda.synchronize()
-    for i, (g, o) in enumerate(zip(gimgs, outs)):
-        v = g.max(dim=2).values.long()
-        lut = ex["lut"][i].long()
-        assert torch.equal(o.max(dim=2).values.long(), lut[v]), i
-    for i, img in kept.items():
-        ref = O.enhance(img, O.Params(bins=256))
-        lut_contract(to_np(ex["lut"][i]), ref)
-        pixel_contract(to_np(outs[i]), ref["out"])
-
-
-def test_full_size_uhd_batch_sampled(H):
-    """The 10-bit workload at full size (8 x 3840x2160 + 8 x 7680x4320, 1024
-    levels) with the schedule the bench uses for it: every image's value
-    channel after remap equals its LUT (exact property at any size), and one
-    3840x2160 image matches the oracle in full."""
-    import multiprocessing as mp
-    import os
-
-    from paper_2510_21100_amd import tune
-
-    n = 16
-    shapes = [(2160, 3840) if i % 2 == 0 else (4320, 7680) for i in range(n)]
-    args = [(config_seed(4, n, i), h, w, 10, 0.3) for i, (h, w) in enumerate(shapes)]
-    # a fresh interpreter per worker: nothing of this process's GPU state is inherited
-    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
-        imgs = pool.starmap(make_image, args)
+def test_batch_rejects_bad_outputs_before_launch(H):
+    """Outputs of the wrong shape, dtype, device or layout raise before
+    anything is enqueued."""
+    imgs = _batch_imgs([(40, 50), (30, 20)])
     gimgs = [to_gpu(x) for x in imgs]
-    kept = {0: imgs[0]}
-    del imgs
-    npix = sum(h * w for h, w in shapes)
-    ws = H.Workspace(max_images=n, max_bins=1024)
-    sched = tune.lookup(os.path.join(os.path.dirname(tune.__file__), "schedule.json"), 1024, 2, npix, n)
-    if sched:
-        ws.set_schedule(*sched)
-    outs, ex = H.enhance_batch(gimgs, H.Params(bins=1024), extras=True, ws=ws)
+    good = [torch.empty_like(g) for g in gimgs]
+    bad_cases = [
+        [good[0]],                                                        # too few
+        [good[0], torch.empty((29, 20, 3), dtype=torch.uint8, device="cuda")],   # fewer rows
+        [good[0], torch.empty((30, 20, 3), dtype=torch.int16, device="cuda")],   # wrong dtype
+        [good[0], torch.empty((30, 20, 3), dtype=torch.uint8)],                  # host memory
+        [good[0], torch.empty((3, 30, 20), dtype=torch.uint8, device="cuda").permute(1, 2, 0)],  # planar
+    ]
+    for outs in bad_cases:
+        with pytest.raises(ValueError):
+            H.enhance_batch(gimgs, H.Params(bins=256), outs=outs)
+    hv, hg, _ = H.build_hist(gimgs[0])
+    with pytest.raises(ValueError):
+        H.solve(hv.cpu(), hg, 40 * 50)
+    with pytest.raises(ValueError):
+        H.match(gimgs[0], hv, torch.ones(256))
     torch.cuda.synchronize()
-    for i, (g, o) in enumerate(zip(gimgs, outs)):
-        v = g.max(dim=2).values.long()
-        lut = ex["lut"][i].long()
-        assert torch.equal(o.max(dim=2).values.long(), lut[v]), i
-    for i, img in kept.items():
-        ref = O.enhance(img, O.Params(bins=1024))
-        assert rel_err(to_np(ex["illum"][i]), ref["illum"]) <= REL_TOL
-        lut_contract(to_np(ex["lut"][i]), ref)
-        pixel_contract(to_np(outs[i]), ref["out"])
-    ws.close()
