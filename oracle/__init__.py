@@ -21,6 +21,7 @@ from .histretinex import (  # noqa: F401
     solve,
     target_histogram,
     matching_lut,
+    equalization_lut,
     remap,
     enhance,
 )

@@ -26,9 +26,13 @@ notes):
   * Eqs. (12)-(13) multiply by K_ij: these are the stationarity conditions of
     Eq. (10) with K frozen, which is how the paper says it derived them;
   * K is 0 where its class total is 0; the initial illumination histogram is
-    the image histogram; the updates run exactly T times in the order of
-    Alg. 1 (R by Eq. 13, then L by Eq. 12 with the new unnormalised R, then the
-    normalisations of Eqs. 15 and 14, then K by Eq. 11);
+    the image histogram; the updates run in the order of Alg. 1 (R by Eq. 13,
+    then L by Eq. 12 with the new unnormalised R, then the normalisations of
+    Eqs. 15 and 14, then K by Eq. 11);
+  * the stopping rule of Alg. 1 is garbled; it is read as: stop after pass
+    t when t = T (the maximum), or earlier when the squared Euclidean norms
+    of the changes of both normalised histograms in that pass, in
+    probability units, are at most eps; eps <= 0 runs exactly T passes;
   * the histogram matching back to pixels maps level v to the smallest target
     level whose cumulative target mass reaches the mid-rank source CDF at v,
     and only the value channel is replaced (hue and saturation kept), which
@@ -46,14 +50,16 @@ import numpy as np
 
 @dataclass(frozen=True)
 class Params:
-    """Method parameters: bins l, iterations T, prior weights alpha, beta of
-    Eq. (10) and the illumination gamma of Eq. (17)."""
+    """Method parameters: bins l, iterations T (the maximum of Alg. 1), prior
+    weights alpha, beta of Eq. (10), the illumination gamma of Eq. (17) and
+    the error threshold eps of Alg. 1 (<= 0: exactly T passes)."""
 
     bins: int = 256
     iters: int = 50
     alpha: float = 0.01
     beta: float = 0.01
     gamma: float = 2.2
+    eps: float = 0.0
 
 
 # --------------------------------------------------------------------------
@@ -232,16 +238,24 @@ def update_step(lv, rv, s, g, idx, alpha, beta, K=None):
 
 
 def solve(hS, hG, params: Params, record: bool = False):
-    """Alg. 1 for exactly ``params.iters`` iterations.
+    """Alg. 1: at most ``params.iters`` passes, fewer when the stopping rule
+    fires (``params.eps`` > 0).
 
     Returns (l, r, info): the normalised illumination and reflectance
-    histograms in probability units and a dict of diagnostics (the per-step
-    objective values and fixed-point residuals when ``record`` is set).
+    histograms in probability units and a dict of diagnostics: "passes" (the
+    passes run), "change_l" / "change_r" (per pass, the squared norm of the
+    change of the normalised L / R), "stop_margin" (the smallest relative
+    distance |max(change_l, change_r) - eps| / eps over the passes whose
+    stopping decision was taken: how far every decision was from flipping;
+    inf when eps <= 0), and with ``record`` the per-step objective values.
     """
     levels = int(params.bins)
     idx = classify(levels)
     s, g, lv, rv = init_state(hS, hG)
-    info = {"J_before": [], "J_after_r": [], "J_after_l": [], "residual": []}
+    eps = float(params.eps)
+    info = {"J_before": [], "J_after_r": [], "J_after_l": [], "residual": [], "change_l": [], "change_r": []}
+    margin = np.inf
+    passes = 0
     _, _, K = weights(lv, rv, idx)
     for _ in range(int(params.iters)):
         step = update_step(lv, rv, s, g, idx, params.alpha, params.beta, K=K)
@@ -253,12 +267,24 @@ def solve(hS, hG, params: Params, record: bool = False):
                                                idx, params.alpha, params.beta))
             info["residual"].append(max(np.abs(step["l"] - lv).max(),
                                         np.abs(step["r"] - rv).max()))
+        change_l = float(((step["l"] - lv) ** 2).sum())
+        change_r = float(((step["r"] - rv) ** 2).sum())
+        info["change_l"].append(change_l)
+        info["change_r"].append(change_r)
         lv, rv = step["l"], step["r"]
+        passes += 1
         _, d, K = weights(lv, rv, idx)  # Eq. (11) for the next pass
         if record:
             tiny = d[(d > 0) & (d < 1e-30)]
             if tiny.size:
                 info.setdefault("tiny_class_totals", []).append(tiny.min())
+        if eps > 0 and passes < int(params.iters):
+            worst = max(change_l, change_r)
+            margin = min(margin, abs(worst - eps) / eps)
+            if worst <= eps:  # both changes at most eps
+                break
+    info["passes"] = passes
+    info["stop_margin"] = margin
     info["d"] = weights(lv, rv, idx)[1]
     return lv, rv, info
 
@@ -312,6 +338,20 @@ def matching_lut(hS, target):
     return lut, margin
 
 
+def equalization_lut(hS):
+    """Classical histogram equalisation (Eq. 5), the comparator of the
+    histogram-domain methods: level i goes to t_i = (l-1) sum_{j<=i} P_C(S)_j
+    with P_C of Eq. (4), rounded to the nearest level (ties upwards).  In
+    integers: t_i = floor((2 (l-1) c_i + N) / (2N)), c_i the running count."""
+    hS = np.asarray(hS, dtype=np.int64)
+    levels = hS.size
+    N = int(hS.sum())
+    if N <= 0:
+        raise ValueError("empty histogram")
+    c = np.cumsum(hS)
+    return (2 * (levels - 1) * c + N) // (2 * N)
+
+
 def remap(img: np.ndarray, lut: np.ndarray) -> np.ndarray:
     """Replace the value channel by LUT[V] keeping hue and saturation:
     out_c = round-half-up(c * LUT[V] / V); black pixels (V = 0) become grey
@@ -347,7 +387,7 @@ def enhance(img: np.ndarray, params: Params = Params(), record: bool = False):
     lut, margin = matching_lut(hS, target)
     out = remap(img, lut)
     return {
-        "V": V, "hS": hS, "graw": graw, "gmax": gmax, "hG": hG,
+        "V": V, "hS": hS, "graw": graw, "gmax": gmax, "hG": hG, "passes": info["passes"],
         "l": lv, "r": rv, "illum": npix * lv, "refl": npix * rv,
         "target": target, "lut": lut, "margin": margin, "out": out,
         "npix": npix, "info": info,
