@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define HR_ABI_VERSION 1
+#define HR_ABI_VERSION 2
 
 typedef enum {
   HR_OK = 0,
@@ -65,17 +65,29 @@ typedef struct {
 } hr_image;
 
 /* Method parameters.
- *  bins  : number of levels l (256 or 1024; must be 2^bits)
- *  iters : T >= 0, the number of Alg. 1 update passes (run exactly T times)
- *  alpha : weight of the illumination prior of Eq. (10), > 0
- *  beta  : weight of the reflectance prior of Eq. (10), > 0
- *  gamma : illumination gamma of Eq. (17), > 0 */
+ *  bins    : number of levels l (256 or 1024; must be 2^bits)
+ *  iters   : T >= 0, the maximum number of Alg. 1 update passes
+ *  alpha   : weight of the illumination prior of Eq. (10), > 0
+ *  beta    : weight of the reflectance prior of Eq. (10), > 0
+ *  gamma   : illumination gamma of Eq. (17), > 0
+ *  eps     : error threshold of Alg. 1's stopping rule, finite.  The rule is
+ *            garbled in the paper; it is read as: stop after pass t when
+ *            t = iters, or earlier when the squared Euclidean norms of the
+ *            changes of both normalised histograms in that pass (L and R in
+ *            probability units, each summing to 1) are at most eps.  eps <= 0
+ *            runs exactly iters passes.  The changes are summed in FP32, so
+ *            an image whose change in some pass lies within FP32 rounding of
+ *            eps may stop one pass away from an FP64 evaluation.
+ *  variant : must be 0 (reserved for variants of the method's readings) */
 typedef struct {
   int32_t bins;
   int32_t iters;
   double alpha;
   double beta;
   double gamma;
+  double eps;
+  uint32_t variant;
+  int32_t reserved; /* must be 0 */
 } hr_params;
 
 /* Launch schedule of the batched form (chosen by the autotuner).  A step is
@@ -139,6 +151,8 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
  *  illum             : device float[bins], out: final H~_C(L) of Eq. (14), counts
  *  refl              : device float[bins], out: final H~_C(R) of Eq. (15), counts
  *  target            : device float[bins], out: H_C(S~) of Eq. (20), counts
+ *  passes            : device int32[1] or NULL, out: the passes run (p->iters,
+ *                      or fewer when the stopping rule of p->eps fired)
  * The updates are Eq. (13) for R then Eq. (12) for L (with the weights K of
  * Eq. (11) multiplying, as in the stationarity conditions of Eq. (10)), then
  * the rescalings of Eqs. (15), (14), starting from R = H_C(grad S) and
@@ -148,8 +162,8 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
  * histograms are used as given; histograms without any mass give zero
  * outputs. */
 hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix,
-                   const hr_params* p, float* illum, float* refl, float* target, hr_workspace* ws,
-                   void* stream);
+                   const hr_params* p, float* illum, float* refl, float* target, int32_t* passes,
+                   hr_workspace* ws, void* stream);
 
 /* Histogram matching of the image to `target` (end of Sec. III-C) and the
  * pixel remap.
@@ -166,6 +180,16 @@ hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, con
                    void* out, int64_t out_row_stride_bytes, uint16_t* lut_out, hr_workspace* ws,
                    void* stream);
 
+/* Classical histogram equalisation (Eq. 5), the comparator the paper
+ * starts from, through the same remap as hr_match: level v goes to the
+ * nearest level of (l-1) * F_S(v) (F_S the image CDF, ties upwards), i.e.
+ * LUT[v] = floor((2 (l-1) c(v) + N) / (2N)) with c the running count of
+ * hist_v and N its total, computed in integers (exact).
+ *  in, bits, hist_v, out, out_row_stride_bytes, lut_out, ws, stream : as hr_match
+ * A hist_v without mass maps every level to 0. */
+hr_status hr_equalize(const hr_image* in, int32_t bits, const uint32_t* hist_v, void* out,
+                      int64_t out_row_stride_bytes, uint16_t* lut_out, hr_workspace* ws, void* stream);
+
 /* ---- the batched form --------------------------------------------------------- */
 
 /* The whole pipeline (hr_build_hist, hr_solve, hr_match) over n images of
@@ -177,11 +201,12 @@ hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, con
  *  luts : device uint16[n][bins] or NULL: per-image level maps, out
  *  illum, refl, target : device float[n][bins] or NULL: per-image solver
  *         outputs, as hr_solve
+ *  passes : device int32[n] or NULL: per-image passes run, as hr_solve
  * n must be in 1..max_images of the workspace. */
 hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes,
                            int32_t n, int32_t bits, const hr_params* p, uint16_t* luts,
-                           float* illum, float* refl, float* target, hr_workspace* ws,
-                           void* stream);
+                           float* illum, float* refl, float* target, int32_t* passes,
+                           hr_workspace* ws, void* stream);
 
 /* ---- the differentiated form (256 levels; not part of the paper) ------------------
  *
@@ -199,6 +224,7 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
 
 /* Alg. 1 for p->iters passes on each of n histogram pairs, keeping the
  * dense (L, R) of t = 0, ckpt_every, ..., iters (probability units).
+ * Runs exactly p->iters passes: p->eps must be <= 0.
  *  hist_v, hist_grad : device uint32[n][256] (from hr_build_hist)
  *  ckpt_every        : 1..16, and p->iters must be a multiple of it
  *  ckpt              : device float[n][iters/ckpt_every + 1][2][256], out:

@@ -12,6 +12,7 @@ from .api import (  # noqa: F401
     build_hist_batch,
     solve,
     match,
+    equalize,
     enhance,
     enhance_batch,
 )

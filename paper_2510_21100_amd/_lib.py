@@ -24,7 +24,7 @@ HR_FLAG_HIST_MASS = 0x2
 #: every symbol the header declares
 EXPORTS = (
     "hr_workspace_create", "hr_workspace_destroy", "hr_workspace_set_schedule", "hr_get_flags",
-    "hr_build_hist", "hr_build_hist_batch", "hr_solve", "hr_match", "hr_enhance_batch",
+    "hr_build_hist", "hr_build_hist_batch", "hr_solve", "hr_match", "hr_equalize", "hr_enhance_batch",
     "hr_solve_ckpt", "hr_softmatch_loss_grad", "hr_solve_vjp",
     "hr_status_string", "hr_last_error", "hr_abi_version",
 )
@@ -37,7 +37,8 @@ class HrImage(C.Structure):
 
 class HrParams(C.Structure):
     _fields_ = [("bins", C.c_int32), ("iters", C.c_int32), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gamma", C.c_double)]
+                ("beta", C.c_double), ("gamma", C.c_double), ("eps", C.c_double),
+                ("variant", C.c_uint32), ("reserved", C.c_int32)]
 
 
 class HrSchedule(C.Structure):
@@ -63,10 +64,11 @@ def _load():
         "hr_get_flags": (C.c_int, [P, u32p, C.c_int32]),
         "hr_build_hist": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, P, P, P]),
         "hr_build_hist_batch": (C.c_int, [C.POINTER(HrImage), C.c_int32, C.c_int32, P, P, P, P]),
-        "hr_solve": (C.c_int, [P, P, C.c_int64, C.POINTER(HrParams), P, P, P, P, P]),
+        "hr_solve": (C.c_int, [P, P, C.c_int64, C.POINTER(HrParams), P, P, P, P, P, P]),
         "hr_match": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, P, C.c_int64, P, P, P]),
+        "hr_equalize": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, C.c_int64, P, P, P]),
         "hr_enhance_batch": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.POINTER(C.c_int64), C.c_int32,
-                                       C.c_int32, C.POINTER(HrParams), P, P, P, P, P, P]),
+                                       C.c_int32, C.POINTER(HrParams), P, P, P, P, P, P, P]),
         "hr_solve_ckpt": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P]),
         "hr_softmatch_loss_grad": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.c_int32, P, P, P, P, P, P]),
         "hr_solve_vjp": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P, P, P]),

@@ -20,16 +20,20 @@ from ._lib import HrImage, HrParams, HrSchedule, check, lib
 
 @dataclass(frozen=True)
 class Params:
-    """bins l, iterations T, prior weights alpha, beta (Eq. 10), gamma (Eq. 17)."""
+    """bins l, the maximum number of passes T, prior weights alpha, beta
+    (Eq. 10), gamma (Eq. 17) and the stopping threshold eps of Alg. 1 (the
+    squared change of both normalised histograms in a pass; <= 0: exactly T
+    passes)."""
 
     bins: int = 256
     iters: int = 50
     alpha: float = 0.01
     beta: float = 0.01
     gamma: float = 2.2
+    eps: float = 0.0
 
     def c(self) -> HrParams:
-        return HrParams(self.bins, self.iters, self.alpha, self.beta, self.gamma)
+        return HrParams(self.bins, self.iters, self.alpha, self.beta, self.gamma, self.eps, 0, 0)
 
 
 def _bits_of(img: torch.Tensor) -> int:
@@ -141,8 +145,9 @@ def build_hist_batch(imgs: Sequence[torch.Tensor], ws: Workspace | None = None):
 
 
 def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Params = Params(),
-          ws: Workspace | None = None):
-    """Returns (illum, refl, target) float32 histograms in counts."""
+          ws: Workspace | None = None, passes: torch.Tensor | None = None):
+    """Returns (illum, refl, target) float32 histograms in counts.  ``passes``
+    (a one-element int32 GPU tensor) receives the number of passes run."""
     ws = ws or workspace()
     bins = params.bins
     if hist_v.numel() != bins or hist_grad.numel() != bins:
@@ -155,9 +160,14 @@ def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Para
     illum = torch.empty(bins, dtype=torch.float32, device=dev)
     refl = torch.empty(bins, dtype=torch.float32, device=dev)
     target = torch.empty(bins, dtype=torch.float32, device=dev)
+    pp = None
+    if passes is not None:
+        if passes.dtype != torch.int32 or passes.numel() < 1:
+            raise ValueError("passes must be an int32 tensor with at least one element")
+        pp = _on_gpu(passes, "passes").data_ptr()
     p = params.c()
     check(lib.hr_solve(hist_v.contiguous().data_ptr(), hist_grad.contiguous().data_ptr(), int(npix), C.byref(p),
-                       illum.data_ptr(), refl.data_ptr(), target.data_ptr(), ws.handle, _stream()))
+                       illum.data_ptr(), refl.data_ptr(), target.data_ptr(), pp, ws.handle, _stream()))
     return illum, refl, target
 
 
@@ -185,6 +195,30 @@ def match(img: torch.Tensor, hist_v: torch.Tensor, target: torch.Tensor, out: to
     return out, lut
 
 
+def equalize(img: torch.Tensor, hist_v: torch.Tensor | None = None, out: torch.Tensor | None = None,
+             ws: Workspace | None = None):
+    """Classical histogram equalisation of Eq. (5) through the same remap as
+    match(); returns (out, lut)."""
+    bits = _bits_of(img)
+    bins = 1 << bits
+    ws = ws or workspace()
+    if hist_v is None:
+        hist_v, _, _ = build_hist(img, ws)
+    if hist_v.numel() != bins or hist_v.dtype != torch.int32:
+        raise ValueError("hist_v must be an int32 histogram of 2^bits entries")
+    _on_gpu(hist_v, "hist_v")
+    if out is None:
+        out = torch.empty_like(img)
+    if out.shape != img.shape or out.dtype != img.dtype:
+        raise ValueError("out must match the image's shape and dtype")
+    lut = torch.empty(bins, dtype=torch.int16, device=img.device)
+    d = _image(img)
+    od = _image(out)
+    check(lib.hr_equalize(C.byref(d), bits, hist_v.contiguous().data_ptr(), C.c_void_p(od.data), od.row_stride_bytes,
+                          lut.data_ptr(), ws.handle, _stream()))
+    return out, lut
+
+
 def enhance(img: torch.Tensor, params: Params | None = None, ws: Workspace | None = None):
     """One image through the whole pipeline, one launch per stage.
     Returns (out, extras) with extras = dict of the intermediate histograms."""
@@ -194,10 +228,11 @@ def enhance(img: torch.Tensor, params: Params | None = None, ws: Workspace | Non
         raise ValueError("params.bins must equal 2^bits of the image")
     hv, hg, hraw = build_hist(img, ws)
     npix = img.shape[0] * img.shape[1]
-    illum, refl, target = solve(hv, hg, npix, params, ws)
+    passes = torch.empty(1, dtype=torch.int32, device=img.device)
+    illum, refl, target = solve(hv, hg, npix, params, ws, passes=passes)
     out, lut = match(img, hv, target, ws=ws)
     return out, {"hist_v": hv, "hist_grad": hg, "hist_grad_raw": hraw, "illum": illum, "refl": refl,
-                 "target": target, "lut": lut}
+                 "target": target, "lut": lut, "passes": passes}
 
 
 def enhance_batch(imgs: Sequence[torch.Tensor], params: Params | None = None,
@@ -227,15 +262,15 @@ def enhance_batch(imgs: Sequence[torch.Tensor], params: Params | None = None,
     arr_out = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
     arr_stride = (C.c_int64 * n)(*[o.stride(0) * o.element_size() for o in outs])
     ex = None
-    ptrs = [None, None, None, None]
+    ptrs = [None, None, None, None, None]
     if extras:
         dev = imgs[0].device
         ex = {"lut": torch.empty((n, bins), dtype=torch.int16, device=dev),
               "illum": torch.empty((n, bins), dtype=torch.float32, device=dev),
               "refl": torch.empty((n, bins), dtype=torch.float32, device=dev),
-              "target": torch.empty((n, bins), dtype=torch.float32, device=dev)}
-        ptrs = [ex["lut"].data_ptr(), ex["illum"].data_ptr(), ex["refl"].data_ptr(), ex["target"].data_ptr()]
+              "target": torch.empty((n, bins), dtype=torch.float32, device=dev),
+              "passes": torch.empty(n, dtype=torch.int32, device=dev)}
+        ptrs = [ex[k].data_ptr() for k in ("lut", "illum", "refl", "target", "passes")]
     p = params.c()
-    check(lib.hr_enhance_batch(arr_in, arr_out, arr_stride, n, bits, C.byref(p), ptrs[0], ptrs[1], ptrs[2],
-                               ptrs[3], ws.handle, _stream()))
+    check(lib.hr_enhance_batch(arr_in, arr_out, arr_stride, n, bits, C.byref(p), *ptrs, ws.handle, _stream()))
     return list(outs), ex

@@ -164,6 +164,9 @@ hr_status check_params(const hr_params* p, int bits) {
   if (!(std::isfinite(p->alpha) && p->alpha > 0)) return fail(HR_ERR_INVALID_ARG, "alpha must be finite and > 0");
   if (!(std::isfinite(p->beta) && p->beta > 0)) return fail(HR_ERR_INVALID_ARG, "beta must be finite and > 0");
   if (!(std::isfinite(p->gamma) && p->gamma > 0)) return fail(HR_ERR_INVALID_ARG, "gamma must be finite and > 0");
+  if (!std::isfinite(p->eps)) return fail(HR_ERR_INVALID_ARG, "eps must be finite");
+  if (p->variant != 0) return fail(HR_ERR_UNSUPPORTED, "unknown variant bits");
+  if (p->reserved != 0) return fail(HR_ERR_INVALID_ARG, "reserved field must be 0");
   return HR_OK;
 }
 
@@ -173,6 +176,7 @@ hr::SolveParams solve_params(const hr_params* p) {
   sp.alpha = (float)p->alpha;
   sp.beta = (float)p->beta;
   sp.inv_gamma = 1.0 / p->gamma;
+  sp.eps = p->eps > 0 ? (float)p->eps : 0.f;
   return sp;
 }
 
@@ -338,7 +342,7 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
 }
 
 hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix, const hr_params* p,
-                   float* illum, float* refl, float* target, hr_workspace* ws, void* stream) {
+                   float* illum, float* refl, float* target, int32_t* passes, hr_workspace* ws, void* stream) {
   hr_status st = check_params(p, 0);
   if (st) return st;
   if (!hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_solve: histogram pointer is NULL");
@@ -346,8 +350,8 @@ hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t np
   if (npix <= 0 || npix >= (1LL << 32) - 1) return fail(HR_ERR_INVALID_ARG, "hr_solve: npix out of range");
   if ((st = check_ws(ws, p->bins))) return st;
   const hr::SolveParams sp = solve_params(p);
-  HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, ws->d_lists, illum, refl, target, ws->d_flags,
-                           static_cast<hipStream_t>(stream)));
+  HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, ws->d_lists, illum, refl, target, passes,
+                           ws->d_flags, static_cast<hipStream_t>(stream)));
   return HR_OK;
 }
 
@@ -368,9 +372,26 @@ hr_status hr_match(const hr_image* in, int32_t bits, const uint32_t* hist_v, con
   return HR_OK;
 }
 
+hr_status hr_equalize(const hr_image* in, int32_t bits, const uint32_t* hist_v, void* out,
+                      int64_t out_row_stride_bytes, uint16_t* lut_out, hr_workspace* ws, void* stream) {
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  const int bins = 1 << bits;
+  hr::ImgDesc d;
+  if ((st = make_desc(in, bits, "hr_equalize", &d))) return st;
+  if ((st = set_out(&d, out, out_row_stride_bytes, bits, "hr_equalize"))) return st;
+  if (!hist_v) return fail(HR_ERR_INVALID_ARG, "hr_equalize: histogram pointer is NULL");
+  if ((st = check_ws(ws, bins))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HR_HIP(hr::launch::equalize_lut(bins, hist_v, ws->d_lut, lut_out, s));
+  const int64_t tile_px = plain_tile_px(bits, d.npix, ws->cu_count, 1);
+  HR_HIP(hr::launch::remap(bits, d, tile_px, ws->d_lut, s));
+  return HR_OK;
+}
+
 hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes, int32_t n,
                            int32_t bits, const hr_params* p, uint16_t* luts, float* illum, float* refl,
-                           float* target, hr_workspace* ws, void* stream) {
+                           float* target, int32_t* passes, hr_workspace* ws, void* stream) {
   hr_status st = check_bits(bits);
   if (st) return st;
   if ((st = check_params(p, bits))) return st;
@@ -416,7 +437,7 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   hdr.tile_px = tile_px;
   hdr.rtile_px = rtile_px;
   hdr.params = solve_params(p);
-  hdr.out = hr::BatchOut{luts, illum, refl, target};
+  hdr.out = hr::BatchOut{luts, illum, refl, target, passes};
   std::memcpy(stage, &hdr, sizeof(hdr));
 
   const int grid = std::max(1, ws->cu_count * ws->sched.wg_per_cu);
@@ -468,6 +489,8 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
 static hr_status check_diff(const hr_params* p, int32_t n, int32_t ckpt_every, const char* what) {
   hr_status st = check_params(p, 8);
   if (st) return st;
+  if (p->eps > 0)
+    return fail(HR_ERR_UNSUPPORTED, std::string(what) + ": the differentiated form runs exactly iters passes (eps <= 0)");
   if (n < 1) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": n must be >= 1");
   if (ckpt_every < 1 || ckpt_every > hr::launch::diff_seg_max())
     return fail(HR_ERR_INVALID_ARG, std::string(what) + ": ckpt_every must be in 1.." +

@@ -1194,7 +1194,7 @@ struct SolveCore {
   int32_t PA[BINS + 1], PB[BINS + 1];               // occupied levels below a / b
   int32_t lane_cells[NT];                           // list build: cells of each lane's rows, then their rank
   int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
-  float redf[4][NT / 64];
+  float redf[6][NT / 64];  // wave partials: sum L^2, sum R'^2, sum R', sum L', change of L, change of R
   uint64_t redu[NT / 64];
   double redd[NT / 64];
   int32_t redi[NT / 64];
@@ -1788,13 +1788,21 @@ __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, 
   }
 }
 
-// The Alg. 1 loop.  LIST: class totals from the class list and sweeps over
-// power-of-two lane groups per output (else class totals from running sums
-// over row runs, four classes per lane, and sweeps with four outputs per lane
-// over input slices); CELLS_LDS / TAB: where the list and the class tables
-// live, so that every access compiles to its address space.
+// The Alg. 1 loop; returns the number of passes run.  LIST: class totals
+// from the class list and sweeps over power-of-two lane groups per output
+// (else class totals from running sums over row runs, four classes per lane,
+// and sweeps with four outputs per lane over input slices); CELLS_LDS / TAB:
+// where the list and the class tables live, so that every access compiles to
+// its address space.
+//
+// Stopping rule (Alg. 1): at most p.iters passes; with p.eps > 0 the loop
+// also ends after a pass whose changes of the normalised L and R both have a
+// squared norm of at most eps.  The normalisation of a pass is folded into
+// the next pass's class sweep, which is where the new L and R meet the old
+// ones: the changes of pass t are summed there, in pass t + 1, and the
+// decision (the same bits in every lane) is taken after its barrier.
 template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
-__device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
+__device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
                         const SolveParams& p, float* ckpt) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
@@ -1861,6 +1869,8 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
   }
   __syncthreads();
 
+  const bool track = p.eps > 0.f;
+  int passes = p.iters;
   for (int it = 0; it < p.iters; ++it) {
     // sums of the previous pass's L', R' (Eqs. 14, 15)
     const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
@@ -2018,17 +2028,36 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
           }
         }
       }
-      float ql = 0.f;
+      float ql = 0.f, dl = 0.f, dr = 0.f;
       for (int i = t; i < nA; i += NT) {
         const float l = sm.lraw[i] * invL;  // Eq. (15)
+        const float e = l - sm.lc[i];       // change of L in the previous pass
+        dl = fmaf(e, e, dl);
         sm.lc[i] = l;
         sm.l2c[i] = l * l;
         ql += l * l;
       }
-      for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] * invR;  // Eq. (14)
+      for (int j = t; j < nB; j += NT) {
+        const float r = sm.rn[j] * invR;  // Eq. (14)
+        const float e = r - sm.rc[j];
+        dr = fmaf(e, e, dr);
+        sm.rc[j] = r;
+      }
       wave_partial<NT>(ql, sm.redf[0]);
+      if (track) {
+        wave_partial<NT>(dl, sm.redf[4]);
+        wave_partial<NT>(dr, sm.redf[5]);
+      }
     }
     __syncthreads();
+    if (track && it > 0) {
+      // stopping rule for the pass just completed (uniform over the block)
+      const float2 ch = block_read2<NT>(sm.redf[4], sm.redf[5]);
+      if (ch.x <= p.eps && ch.y <= p.eps) {
+        passes = it;
+        break;
+      }
+    }
     // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta)
     {
       const float invD = 1.f / (block_read<NT>(sm.redf[0]) + p.beta);
@@ -2120,6 +2149,7 @@ __device__ __forceinline__ void iterate(SolveSmem<BINS, NT, BUDGET>& sm, const t
     for (int j = t; j < nB; j += NT) sm.rc[j] = sm.rn[j] * invR;
   }
   __syncthreads();
+  return passes;
 }
 
 // LDS budget of the one-image solver: most of a CU's 160 KB.
@@ -2183,16 +2213,18 @@ __device__ uint64_t solve_setup(const uint32_t* hS, const uint32_t* hG, int64_t 
   return Ns;
 }
 
-// Alg. 1 (Eqs. 11-15) for p.iters passes and the target histogram of
+// Alg. 1 (Eqs. 11-15) for at most p.iters passes and the target histogram of
 // Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); gcells:
 // global scratch (gcap cells) for the class list when it does not fit in
-// LDS.  Writes illum/refl/target (counts, dense over the l levels) when
-// non-null, and with ckpt non-null and p.ckpt_every > 0 the dense (L, R) of
-// t = 0, every, 2 every, ... (2 l floats each, see write_state).
+// LDS.  Writes illum/refl/target (counts, dense over the l levels) and the
+// number of passes run when non-null, and with ckpt non-null and
+// p.ckpt_every > 0 the dense (L, R) of t = 0, every, 2 every, ... (2 l floats
+// each, see write_state).
 template <int BINS, int NT, int BUDGET, bool MAY_BE_EMPTY = true>
 __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
                             SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
-                            float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr) {
+                            float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr,
+                            int32_t* passes_out = nullptr) {
   const int t = threadIdx.x;
   const uint64_t Ns = solve_setup<BINS, NT>(hS, hG, npix, sm, flags);
   const int nA = sm.nA, nB = sm.nB;
@@ -2206,18 +2238,20 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
     }
     if (ckpt && p.ckpt_every > 0)
       for (int64_t k = t; k < (int64_t)(p.iters / p.ckpt_every + 1) * 2 * BINS; k += NT) ckpt[k] = 0.f;
+    if (passes_out && t == 0) *passes_out = 0;
     return;
   }
+  int passes;
   if constexpr (BINS == 256) {
     build_class_list<BINS, NT, BUDGET>(sm, gcells, gcap);
     if (!sm.use_list)
-      iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
     else if (!sm.cells_lds)
-      iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p, ckpt);
     else if (sm.tab_lds)
-      iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p, ckpt);
     else
-      iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p, ckpt);
   } else {
     if (t == 0) {
       sm.C = 0;
@@ -2227,8 +2261,9 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
       sm.nBp = (nB + 3) & ~3;
     }
     __syncthreads();
-    iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
+    passes = iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
   }
+  if (passes_out && t == 0) *passes_out = passes;
 
   // Eqs. (17)-(20): target_k = N * sum over cells with round(theta_a * b) = k
   // of L_a R_b.  Products of two floats are exact in FP64; they are summed in

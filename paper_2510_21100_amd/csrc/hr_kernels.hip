@@ -47,8 +47,8 @@ __global__ __launch_bounds__(NT_PIX) void k_hist(ImgDesc d, int64_t tile_px, uin
 }
 
 constexpr int NT_BATCH = NT_SOLVE;
-// The batched kernel's register use allows one 512-thread workgroup per CU,
-// so its solver can take most of the CU's LDS as well.
+// One 1024-thread batched workgroup per CU (its pixel loops and solver take
+// most of the CU's registers), so its solver can take most of the CU's LDS.
 template <int BITS> struct BatchBudget {
   static constexpr int value = 150 * 1024;
 };
@@ -56,11 +56,30 @@ template <int BITS> struct BatchBudget {
 template <int BINS, int NT>
 __global__ __launch_bounds__(NT) void k_solve(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
                                               uint32_t* lists, float* illum, float* refl, float* target,
-                                              uint32_t* flags) {
+                                              int32_t* passes, uint32_t* flags) {
   __shared__ SolveSmem<BINS, NT, SOLVE_BUDGET_PLAIN> sm;
   solve_image<BINS, NT, SOLVE_BUDGET_PLAIN>(
       hS, hG, npix, p, sm, reinterpret_cast<typename CellT<BINS>::type*>(lists),
-      (int64_t)LIST_WORDS<BINS> * 4 / (int64_t)sizeof(typename CellT<BINS>::type), illum, refl, target, flags);
+      (int64_t)LIST_WORDS<BINS> * 4 / (int64_t)sizeof(typename CellT<BINS>::type), illum, refl, target, flags,
+      nullptr, passes);
+}
+
+// Classical histogram equalisation (Eq. 5): level v goes to the nearest
+// level of (l-1) c(v) / N, ties upwards, c the running count: in integers
+// floor((2 (l-1) c(v) + N) / (2N)).  One workgroup; the running count is an
+// exact integer scan.
+template <int BINS, int NT>
+__global__ __launch_bounds__(NT) void k_he_lut(const uint32_t* hS, uint16_t* lut, uint16_t* lut_user) {
+  __shared__ uint64_t c[BINS];
+  __shared__ uint64_t red[NT / 64];
+  for (int k = threadIdx.x; k < BINS; k += NT) c[k] = hS[k];
+  __syncthreads();
+  const uint64_t N = block_scan<NT, uint64_t, true>(c, BINS, red);
+  for (int k = threadIdx.x; k < BINS; k += NT) {
+    const uint16_t v = N ? (uint16_t)((2ull * (BINS - 1) * c[k] + N) / (2ull * N)) : (uint16_t)0;
+    lut[k] = v;
+    if (lut_user) lut_user[k] = v;
+  }
 }
 
 template <int BINS, int NT>
@@ -183,7 +202,7 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
       reinterpret_cast<typename CellT<BINS>::type*>(lists_base + (int64_t)i * lists_stride),
       lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),
       out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
-      tgt, flags);
+      tgt, flags, nullptr, out.passes ? out.passes + slot : nullptr);
   drain_memory();
   __syncthreads();
   uint16_t* lut = s->lut(BINS);
@@ -383,14 +402,23 @@ hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, i
 }
 
 hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
-                 uint32_t* lists, float* illum, float* refl, float* target, uint32_t* flags, hipStream_t s) {
+                 uint32_t* lists, float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags,
+                 hipStream_t s) {
   // same workgroup shape as the batched kernel's solver: identical results
   if (bins == 256)
     hipLaunchKernelGGL((k_solve<256, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
-                       refl, target, flags);
+                       refl, target, passes, flags);
   else
     hipLaunchKernelGGL((k_solve<1024, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
-                       refl, target, flags);
+                       refl, target, passes, flags);
+  return hipGetLastError();
+}
+
+hipError_t equalize_lut(int bins, const uint32_t* hS, uint16_t* lut, uint16_t* lut_user, hipStream_t s) {
+  if (bins == 256)
+    hipLaunchKernelGGL((k_he_lut<256, 256>), dim3(1), dim3(256), 0, s, hS, lut, lut_user);
+  else
+    hipLaunchKernelGGL((k_he_lut<1024, 256>), dim3(1), dim3(256), 0, s, hS, lut, lut_user);
   return hipGetLastError();
 }
 

@@ -27,11 +27,13 @@ struct ImgDesc {
 
 // Solver parameters as the kernels take them.
 struct SolveParams {
-  int32_t iters;
+  int32_t iters;       // the maximum number of passes T
   float alpha;
   float beta;
   int32_t ckpt_every;  // differentiated form: checkpoint interval (0: none)
   double inv_gamma;
+  float eps;           // stopping threshold of Alg. 1 (<= 0: exactly iters passes)
+  int32_t pad;
 };
 
 // Optional per-image outputs of the batched form, indexed by the caller's slot.
@@ -40,6 +42,7 @@ struct BatchOut {
   float* illum;
   float* refl;
   float* target;
+  int32_t* passes;
 };
 
 // Header of the batched descriptor table (device copy written per call, so a
@@ -93,7 +96,9 @@ hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint3
 hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, int64_t tile_px, uint32_t* hs,
                       uint32_t* hg, ImageState* st, uint32_t* flags, hipStream_t s);
 hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
-                 uint32_t* lists, float* illum, float* refl, float* target, uint32_t* flags, hipStream_t s);
+                 uint32_t* lists, float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags,
+                 hipStream_t s);
+hipError_t equalize_lut(int bins, const uint32_t* hS, uint16_t* lut, uint16_t* lut_user, hipStream_t s);
 hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut, uint16_t* lut_user,
                hipStream_t s);
 hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lut, hipStream_t s);

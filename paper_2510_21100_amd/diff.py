@@ -31,7 +31,7 @@ def _ptr(t: torch.Tensor) -> C.c_void_p:
 
 
 def _params(alpha: float, beta: float, iters: int, gamma: float):
-    return api.Params(bins=BINS, iters=iters, alpha=alpha, beta=beta, gamma=gamma).c()
+    return api.Params(bins=BINS, iters=iters, alpha=alpha, beta=beta, gamma=gamma, eps=0.0).c()
 
 
 class TargetFn(torch.autograd.Function):

@@ -96,12 +96,12 @@ def test_build_hist_batch_validation(L):
     assert "workspace" in _err(L)
 
 
-def _params(L, bins=256, iters=50, alpha=0.01, beta=0.01, gamma=2.2):
-    return L.HrParams(bins, iters, alpha, beta, gamma)
+def _params(L, bins=256, iters=50, alpha=0.01, beta=0.01, gamma=2.2, eps=0.0, variant=0, reserved=0):
+    return L.HrParams(bins, iters, alpha, beta, gamma, eps, variant, reserved)
 
 
 def _solve(L, p):
-    return L.lib.hr_solve(0x2000, 0x3000, 100, C.byref(p), 0x4000, 0x5000, 0x6000, None, None)
+    return L.lib.hr_solve(0x2000, 0x3000, 100, C.byref(p), 0x4000, 0x5000, 0x6000, None, None, None)
 
 
 def test_solve_validation(L):
@@ -111,10 +111,19 @@ def test_solve_validation(L):
     assert _solve(L, _params(L, beta=-1.0)) == L.HR_ERR_INVALID_ARG
     assert _solve(L, _params(L, gamma=float("nan"))) == L.HR_ERR_INVALID_ARG
     assert _solve(L, _params(L, alpha=float("inf"))) == L.HR_ERR_INVALID_ARG
-    assert L.lib.hr_solve(0x2000, 0x3000, 100, None, 0x4000, 0x5000, 0x6000, None, None) == L.HR_ERR_INVALID_ARG
+    assert _solve(L, _params(L, eps=float("nan"))) == L.HR_ERR_INVALID_ARG
+    assert _solve(L, _params(L, variant=1)) == L.HR_ERR_UNSUPPORTED
+    assert _solve(L, _params(L, reserved=3)) == L.HR_ERR_INVALID_ARG
+    assert L.lib.hr_solve(0x2000, 0x3000, 100, None, 0x4000, 0x5000, 0x6000, None, None, None) == L.HR_ERR_INVALID_ARG
     p = _params(L)
-    assert L.lib.hr_solve(None, 0x3000, 100, C.byref(p), 0x4000, 0x5000, 0x6000, None, None) == L.HR_ERR_INVALID_ARG
-    assert L.lib.hr_solve(0x2000, 0x3000, 100, C.byref(p), None, 0x5000, 0x6000, None, None) == L.HR_ERR_INVALID_ARG
+    assert L.lib.hr_solve(None, 0x3000, 100, C.byref(p), 0x4000, 0x5000, 0x6000, None, None, None) \
+        == L.HR_ERR_INVALID_ARG
+    assert L.lib.hr_solve(0x2000, 0x3000, 100, C.byref(p), None, 0x5000, 0x6000, None, None, None) \
+        == L.HR_ERR_INVALID_ARG
+    # eps > 0 and negative eps are both valid (negative: exactly iters passes)
+    for eps in (1e-5, -1.0):
+        assert _solve(L, _params(L, eps=eps)) == L.HR_ERR_INVALID_ARG
+        assert "workspace" in _err(L)
     assert _solve(L, p) == L.HR_ERR_INVALID_ARG  # no workspace
     assert "workspace" in _err(L)
 
@@ -128,6 +137,18 @@ def test_match_validation(L):
     assert "workspace" in _err(L)
 
 
+def test_equalize_validation(L):
+    img = _img()
+    f = L.lib.hr_equalize
+    assert f(None, 8, 0x2000, 0x7000, 192, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 9, 0x2000, 0x7000, 192, None, None, None) == L.HR_ERR_UNSUPPORTED
+    assert f(C.byref(img), 8, None, 0x7000, 192, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 8, 0x2000, None, 192, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 8, 0x2000, 0x7000, 191, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 8, 0x2000, 0x7000, 192, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert "workspace" in _err(L)
+
+
 def test_enhance_batch_validation(L):
     n = 2
     imgs = (L.HrImage * n)(_img(), _img(w=100, h=50))
@@ -135,12 +156,12 @@ def test_enhance_batch_validation(L):
     strides = (C.c_int64 * n)(3 * 64, 3 * 100)
     p = _params(L)
     f = L.lib.hr_enhance_batch
-    assert f(imgs, outs, strides, 0, 8, C.byref(p), None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
-    assert f(None, outs, strides, n, 8, C.byref(p), None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
-    assert f(imgs, outs, strides, n, 10, C.byref(p), None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(imgs, outs, strides, 0, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(None, outs, strides, n, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(imgs, outs, strides, n, 10, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
     bad = (C.c_int64 * n)(3 * 64, 3 * 100 - 3)
-    assert f(imgs, outs, bad, n, 8, C.byref(p), None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
-    assert f(imgs, outs, strides, n, 8, C.byref(p), None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(imgs, outs, bad, n, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(imgs, outs, strides, n, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
     assert "workspace" in _err(L)
 
 
