@@ -47,11 +47,12 @@ def pool_size(bytes_per_worker: int) -> int:
 
 def check_all(tasks, bytes_per_worker: int):
     """Runs check_image over tasks in a spawn pool; returns the results in
-    image order and prints one line per image."""
+    image order and prints one line per image as it ends."""
+    res = []
     with mp.get_context("spawn").Pool(pool_size(bytes_per_worker), maxtasksperchild=4) as pool:
-        res = sorted(pool.imap_unordered(check_image, tasks), key=lambda r: r["i"])
-    for r in res:
-        print(f"image {r['i']:3d}: {r['npix']:9d} px  illum {r['illum_err']:.2e}  refl {r['refl_err']:.2e}  "
-              f"target {r['target_err']:.2e}  near-tie levels {r['near_ties']}  pixels off {r['off_frac']:.2e}",
-              flush=True)
-    return res
+        for r in pool.imap_unordered(check_image, tasks):
+            print(f"image {r['i']:3d}: {r['npix']:9d} px  illum {r['illum_err']:.2e}  refl {r['refl_err']:.2e}  "
+                  f"target {r['target_err']:.2e}  near-tie levels {r['near_ties']}  pixels off {r['off_frac']:.2e}",
+                  flush=True)
+            res.append(r)
+    return sorted(res, key=lambda r: r["i"])
