@@ -208,6 +208,29 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
                            float* illum, float* refl, float* target, int32_t* passes,
                            hr_workspace* ws, void* stream);
 
+/* hr_enhance_batch for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Takes no workspace and allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library routine): the descriptor table travels as
+ * a kernel argument, and the queue, counters, per-image states and solver
+ * scratch live in one fixed device array of the library, about 3.6 MB on
+ * each GPU it runs on, held until the process ends.  Every call on a GPU
+ * shares that array: two calls that overlap on one GPU (different streams,
+ * or threads without ordering) race; calls ordered on one stream do not.
+ * Each call clears what must start at zero.  Results are those of
+ * hr_enhance_batch with the default schedule (bit for bit).
+ *  in, out, out_row_stride_bytes, bits, p, luts, illum, refl, target,
+ *  passes : as hr_enhance_batch
+ *  n      : 1..HR_NOALLOC_MAX_IMAGES; more is refused with HR_ERR_UNSUPPORTED
+ *  flags  : device uint32[1] or NULL: the sticky device flags of the call are
+ *           OR-ed into it (the caller clears it; NULL: not reported)
+ *  stream : as everywhere; the call enqueues two kernels on it */
+#define HR_NOALLOC_MAX_IMAGES 4
+hr_status hr_enhance_batch_noalloc(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes,
+                                   int32_t n, int32_t bits, const hr_params* p, uint16_t* luts,
+                                   float* illum, float* refl, float* target, int32_t* passes,
+                                   uint32_t* flags, void* stream);
+
 /* ---- the differentiated form (256 levels; not part of the paper) ------------------
  *
  * Gradients of an enhancement loss with respect to the prior weights alpha,

@@ -15,4 +15,5 @@ from .api import (  # noqa: F401
     equalize,
     enhance,
     enhance_batch,
+    enhance_batch_noalloc,
 )

@@ -20,11 +20,13 @@ HR_ERR_WORKSPACE = 3
 HR_ERR_DEVICE = 4
 HR_FLAG_VALUE_CLAMPED = 0x1
 HR_FLAG_HIST_MASS = 0x2
+HR_NOALLOC_MAX_IMAGES = 4
 
 #: every symbol the header declares
 EXPORTS = (
     "hr_workspace_create", "hr_workspace_destroy", "hr_workspace_set_schedule", "hr_get_flags",
     "hr_build_hist", "hr_build_hist_batch", "hr_solve", "hr_match", "hr_equalize", "hr_enhance_batch",
+    "hr_enhance_batch_noalloc",
     "hr_solve_ckpt", "hr_softmatch_loss_grad", "hr_solve_vjp",
     "hr_status_string", "hr_last_error", "hr_abi_version",
 )
@@ -69,6 +71,8 @@ def _load():
         "hr_equalize": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, C.c_int64, P, P, P]),
         "hr_enhance_batch": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.POINTER(C.c_int64), C.c_int32,
                                        C.c_int32, C.POINTER(HrParams), P, P, P, P, P, P, P]),
+        "hr_enhance_batch_noalloc": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.POINTER(C.c_int64), C.c_int32,
+                                               C.c_int32, C.POINTER(HrParams), P, P, P, P, P, P, P]),
         "hr_solve_ckpt": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P]),
         "hr_softmatch_loss_grad": (C.c_int, [C.POINTER(HrImage), C.POINTER(P), C.c_int32, P, P, P, P, P, P]),
         "hr_solve_vjp": (C.c_int, [P, P, C.c_int32, C.POINTER(HrParams), C.c_int32, P, P, P, P, P, P]),

@@ -274,3 +274,51 @@ def enhance_batch(imgs: Sequence[torch.Tensor], params: Params | None = None,
     p = params.c()
     check(lib.hr_enhance_batch(arr_in, arr_out, arr_stride, n, bits, C.byref(p), *ptrs, ws.handle, _stream()))
     return list(outs), ex
+
+
+def enhance_batch_noalloc(imgs: Sequence[torch.Tensor], outs: Sequence[torch.Tensor], params: Params | None = None,
+                          extras: dict | None = None, flags: torch.Tensor | None = None) -> None:
+    """hr_enhance_batch_noalloc: up to HR_NOALLOC_MAX_IMAGES images through the
+    batched pipeline without any device allocation by the library (its scratch
+    is a fixed device array shared by every call on the GPU).  The caller
+    provides the outputs: ``outs`` (one per image), optionally ``extras`` with
+    any of the keys lut, illum, refl, target (n, bins) and passes (n), and
+    ``flags`` (one int32/uint32 element that receives the sticky flags)."""
+    n = len(imgs)
+    if n == 0:
+        raise ValueError("empty batch")
+    bits = _bits_of(imgs[0])
+    if any(_bits_of(x) != bits for x in imgs):
+        raise ValueError("all images of a batch must have the same bit depth")
+    bins = 1 << bits
+    params = params or Params(bins=bins)
+    if len(outs) != n:
+        raise ValueError("one output per image")
+    arr_in = (HrImage * n)(*[_image(x) for x in imgs])
+    for x, o in zip(imgs, outs):
+        _image(o)
+        if o.shape != x.shape or o.dtype != x.dtype:
+            raise ValueError("each output must match its image's shape and dtype")
+    arr_out = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    arr_stride = (C.c_int64 * n)(*[o.stride(0) * o.element_size() for o in outs])
+    extras = extras or {}
+    want = {"lut": ((n, bins), (torch.int16, torch.uint16)), "illum": ((n, bins), (torch.float32,)),
+            "refl": ((n, bins), (torch.float32,)), "target": ((n, bins), (torch.float32,)),
+            "passes": ((n,), (torch.int32,))}
+    ptrs = []
+    for k in ("lut", "illum", "refl", "target", "passes"):
+        t = extras.get(k)
+        if t is None:
+            ptrs.append(None)
+            continue
+        shape, dtypes = want[k]
+        if tuple(t.shape) != shape or t.dtype not in dtypes or not t.is_contiguous():
+            raise ValueError(f"extras[{k!r}] must be a contiguous {shape} tensor of {dtypes[0]}")
+        ptrs.append(_on_gpu(t, k).data_ptr())
+    fp = None
+    if flags is not None:
+        if flags.numel() < 1 or flags.dtype not in (torch.int32, torch.uint32):
+            raise ValueError("flags must be an int32 tensor with at least one element")
+        fp = _on_gpu(flags, "flags").data_ptr()
+    p = params.c()
+    check(lib.hr_enhance_batch_noalloc(arr_in, arr_out, arr_stride, n, bits, C.byref(p), *ptrs, fp, _stream()))

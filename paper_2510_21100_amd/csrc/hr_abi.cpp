@@ -483,6 +483,49 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   return HR_OK;
 }
 
+hr_status hr_enhance_batch_noalloc(const hr_image* in, void* const* out, const int64_t* out_row_stride_bytes,
+                                   int32_t n, int32_t bits, const hr_params* p, uint16_t* luts, float* illum,
+                                   float* refl, float* target, int32_t* passes, uint32_t* flags, void* stream) {
+  static_assert(HR_NOALLOC_MAX_IMAGES == hr::NOALLOC_MAX_IMAGES, "header and library agree on the limit");
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  if ((st = check_params(p, bits))) return st;
+  if (!in || !out || !out_row_stride_bytes) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch_noalloc: NULL array");
+  if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch_noalloc: n must be >= 1");
+  if (n > hr::NOALLOC_MAX_IMAGES)
+    return fail(HR_ERR_UNSUPPORTED, "hr_enhance_batch_noalloc: n exceeds HR_NOALLOC_MAX_IMAGES (" +
+                                        std::to_string(hr::NOALLOC_MAX_IMAGES) + ")");
+  hr::ImgDesc descs[hr::NOALLOC_MAX_IMAGES];
+  for (int i = 0; i < n; ++i) {
+    if ((st = make_desc(&in[i], bits, "hr_enhance_batch_noalloc", &descs[i]))) return st;
+    if ((st = set_out(&descs[i], out[i], out_row_stride_bytes[i], bits, "hr_enhance_batch_noalloc"))) return st;
+    descs[i].slot = i;
+  }
+  // the queue order and item sizes of hr_enhance_batch with the default schedule
+  int order[hr::NOALLOC_MAX_IMAGES];
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order, order + n, [&](int a, int b) { return descs[a].npix > descs[b].npix; });
+  const int64_t tile_px = (int64_t)kDefaultTileSteps * hr::launch::batch_step_px(bits);
+  const int64_t rtile_px = (int64_t)kDefaultRemapSteps * hr::launch::batch_step_px(bits);
+  hr::NoallocTable t{};
+  int64_t tiles = 0;
+  for (int k = 0; k < n; ++k) {
+    hr::ImgDesc d = descs[order[k]];
+    d.ntiles = (int32_t)((d.npix + tile_px - 1) / tile_px);
+    d.tile0 = (int32_t)tiles;
+    d.rtiles = (int32_t)((d.npix + rtile_px - 1) / rtile_px);
+    tiles += d.ntiles;
+    t.desc[k] = d;
+  }
+  t.hdr.n = n;
+  t.hdr.total_tiles = (int32_t)tiles;
+  t.hdr.tile_px = tile_px;
+  t.hdr.rtile_px = rtile_px;
+  t.hdr.params = solve_params(p);
+  t.hdr.out = hr::BatchOut{luts, illum, refl, target, passes};
+  HR_HIP(hr::launch::batch_noalloc(bits, kDefaultWgPerCu, t, flags, static_cast<hipStream_t>(stream)));
+  return HR_OK;
+}
 
 // ---- differentiated form -------------------------------------------------------
 

@@ -11,6 +11,7 @@
 #include "hr_launch.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace hr {
 
@@ -367,6 +368,62 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free batched form: fixed scratch in the library's own device array
+// ---------------------------------------------------------------------------
+
+// Layout of the scratch array (bytes): the flags word the kernels write when
+// the caller passes none, the descriptor table (header, descriptors, counters),
+// the per-image states (room for NOALLOC_MAX_IMAGES states of the larger,
+// 1024-level layout; a call strides them by the layout of its own level
+// count, as the batched kernel does), the solver's class-list scratch (256
+// levels only: 1024 levels never use it).
+constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+struct NoallocLayout {
+  static constexpr int64_t FLAGS = 0;
+  static constexpr int64_t TABLE = 256;
+  static constexpr int64_t TABLE_BYTES =
+      sizeof(BatchHeader) + NOALLOC_MAX_IMAGES * (sizeof(ImgDesc) + sizeof(ImgCounters));
+  static constexpr int64_t STATE = align256(TABLE + TABLE_BYTES);
+  static constexpr int64_t STATE_WORDS = ImageState::words(1024);  // per image
+  static constexpr int64_t LISTS = align256(STATE + 4 * STATE_WORDS * NOALLOC_MAX_IMAGES);
+  static constexpr int64_t LIST_WORDS_256 = LIST_WORDS<256>;  // per image
+  static constexpr int64_t BYTES = align256(LISTS + 4 * LIST_WORDS_256 * NOALLOC_MAX_IMAGES);
+};
+
+// The scratch itself, about 3.6 MB on every GPU the library runs on, held
+// until the process ends.  Host code never passes this name to a kernel: it
+// is a host-side stand-in; the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t scratch[NoallocLayout::BYTES];
+
+// Writes the call's descriptor table into the scratch (header, descriptors,
+// zero counters) and zeroes the partial histogram slots of its images in the
+// layout of this bit depth (a previous call may have left another layout, or
+// have been cut short).  Grid-stride over every block.
+template <int BITS>
+__global__ __launch_bounds__(256) void k_noalloc_setup(NoallocTable t, uint8_t* base) {
+  constexpr int BINS = Cfg<BITS>::BINS;
+  auto* hdr = reinterpret_cast<BatchHeader*>(base + NoallocLayout::TABLE);
+  auto* desc = reinterpret_cast<ImgDesc*>(base + NoallocLayout::TABLE + sizeof(BatchHeader));
+  auto* ctr = reinterpret_cast<ImgCounters*>(base + NoallocLayout::TABLE + sizeof(BatchHeader) +
+                                             NOALLOC_MAX_IMAGES * sizeof(ImgDesc));
+  const int n = t.hdr.n;
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  if (tid == 0) *hdr = t.hdr;
+  if (tid < n) {
+    desc[tid] = t.desc[tid];
+    ctr[tid] = ImgCounters{0u, 0u, 0u, 0u};
+  }
+  constexpr int64_t SLOT_WORDS = (int64_t)ImageState::NSLOT * 3 * BINS;
+  for (int64_t q = tid; q < (int64_t)n * SLOT_WORDS; q += nthreads) {
+    const int i = (int)(q / SLOT_WORDS);
+    // the batched kernel's state stride: words(BINS) of this bit depth
+    auto* st = reinterpret_cast<ImageState*>(base + NoallocLayout::STATE + 4 * ImageState::words(BINS) * i);
+    st->slot(BINS, 0)[q - i * SLOT_WORDS] = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -455,6 +512,68 @@ hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgC
 int step_px(int bits) { return bits == 8 ? Pix<8, NT_PIX>::STEP : Pix<10, NT_PIX>::STEP; }
 int batch_step_px(int bits) { return bits == 8 ? Pix<8, NT_BATCH>::STEP : Pix<10, NT_BATCH>::STEP; }
 int max_width(int bits) { return bits == 8 ? MaxWidth<8>::value : MaxWidth<10>::value; }
+
+int64_t noalloc_scratch_bytes() { return NoallocLayout::BYTES; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch[kMaxDevices] = {};  // device address of `scratch` on each GPU
+int g_cus[kMaxDevices] = {};
+
+// The scratch array's device address and the CU count of the current GPU,
+// looked up once per device (with that device current) and kept.
+hipError_t scratch_of_current_device(uint8_t** ptr, int* cus) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    int n = 0;
+    e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    g_cus[dev] = n;
+    g_scratch[dev] = static_cast<uint8_t*>(p);
+  }
+  *ptr = g_scratch[dev];
+  *cus = g_cus[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t batch_noalloc(int bits, int grid_per_cu, const NoallocTable& t, uint32_t* flags_user, hipStream_t s) {
+  uint8_t* base = nullptr;
+  int cus = 0;
+  hipError_t e = scratch_of_current_device(&base, &cus);
+  if (e != hipSuccess) return e;
+  auto* hdr = reinterpret_cast<BatchHeader*>(base + NoallocLayout::TABLE);
+  auto* desc = reinterpret_cast<ImgDesc*>(base + NoallocLayout::TABLE + sizeof(BatchHeader));
+  auto* ctr = reinterpret_cast<ImgCounters*>(base + NoallocLayout::TABLE + sizeof(BatchHeader) +
+                                             NOALLOC_MAX_IMAGES * sizeof(ImgDesc));
+  auto* st = reinterpret_cast<ImageState*>(base + NoallocLayout::STATE);
+  auto* lists = reinterpret_cast<uint32_t*>(base + NoallocLayout::LISTS);
+  uint32_t* flags = flags_user ? flags_user : reinterpret_cast<uint32_t*>(base + NoallocLayout::FLAGS);
+  // the kernels stride the states by words(bins) of the call's level count
+  static_assert(NoallocLayout::STATE_WORDS >= ImageState::words(256), "state layout");
+  const int grid = std::max(1, cus * std::max(1, grid_per_cu));
+  if (bits == 8) {
+    hipLaunchKernelGGL(k_noalloc_setup<8>, dim3(16), dim3(256), 0, s, t, base);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists,
+                       (int64_t)LIST_WORDS<256>, flags);
+  } else {
+    hipLaunchKernelGGL(k_noalloc_setup<10>, dim3(16), dim3(256), 0, s, t, base);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, (int64_t)0,
+                       flags);
+  }
+  return hipGetLastError();
+}
 
 }  // namespace launch
 }  // namespace hr

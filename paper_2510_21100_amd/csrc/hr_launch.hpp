@@ -89,6 +89,15 @@ struct ImageState {
   __host__ __device__ uint32_t* slot(int bins, int k) { return base() + 4 + 5 * bins + bins / 2 + k * 3 * bins; }
 };
 
+// Allocation-free form of the batched call: the descriptor table travels as a
+// kernel argument and every buffer the kernels need lives in one fixed device
+// array of the library (per GPU), so at most NOALLOC_MAX_IMAGES images per call.
+constexpr int NOALLOC_MAX_IMAGES = 4;
+struct NoallocTable {
+  BatchHeader hdr;
+  ImgDesc desc[NOALLOC_MAX_IMAGES];
+};
+
 namespace launch {
 hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint32_t* graw, uint32_t* hg,
@@ -115,6 +124,11 @@ hipError_t softmatch(int n, const ImgDesc* desc, int64_t max_npix, const uint32_
 hipError_t solve_vjp(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, const float* ckpt,
                      const float* dtarget, double* dalpha, double* dbeta, uint32_t* flags, hipStream_t s);
 int diff_seg_max();
+// The batched kernel on the library's own fixed scratch (no allocation): t
+// holds the header and the n descriptors in queue order; flags_user (device,
+// may be NULL) receives the sticky flags.  Calls on one GPU share the scratch.
+hipError_t batch_noalloc(int bits, int grid_per_cu, const NoallocTable& t, uint32_t* flags_user, hipStream_t s);
+int64_t noalloc_scratch_bytes();
 }  // namespace launch
 
 }  // namespace hr

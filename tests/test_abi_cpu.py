@@ -165,6 +165,28 @@ def test_enhance_batch_validation(L):
     assert "workspace" in _err(L)
 
 
+def test_enhance_batch_noalloc_validation(L):
+    """Refusals of the allocation-free call happen on the host, before any
+    device call: more images than HR_NOALLOC_MAX_IMAGES, bad descriptors."""
+    f = L.lib.hr_enhance_batch_noalloc
+    p = _params(L)
+    n = L.HR_NOALLOC_MAX_IMAGES + 1
+    imgs = (L.HrImage * n)(*[_img() for _ in range(n)])
+    outs = (C.c_void_p * n)(*[0x8000 + 0x1000 * i for i in range(n)])
+    strides = (C.c_int64 * n)(*[3 * 64] * n)
+    args = (None, None, None, None, None, None, None)
+    assert f(imgs, outs, strides, n, 8, C.byref(p), *args) == L.HR_ERR_UNSUPPORTED
+    assert "HR_NOALLOC_MAX_IMAGES" in _err(L)
+    assert f(imgs, outs, strides, 0, 8, C.byref(p), *args) == L.HR_ERR_INVALID_ARG
+    assert f(None, outs, strides, 2, 8, C.byref(p), *args) == L.HR_ERR_INVALID_ARG
+    assert f(imgs, outs, strides, 2, 10, C.byref(p), *args) == L.HR_ERR_INVALID_ARG  # bins != 2^bits
+    bad = (C.c_int64 * n)(3 * 64, 3 * 64 - 3, 3 * 64, 3 * 64, 3 * 64)
+    assert f(imgs, outs, bad, 2, 8, C.byref(p), *args) == L.HR_ERR_INVALID_ARG
+    assert "stride" in _err(L)
+    header = open(HEADER).read()
+    assert int(re.search(r"#define HR_NOALLOC_MAX_IMAGES (\d+)", header).group(1)) == L.HR_NOALLOC_MAX_IMAGES
+
+
 def test_workspace_calls_reject_null(L):
     s = L.HrSchedule(4, 1, 8)
     assert L.lib.hr_workspace_set_schedule(None, C.byref(s)) == L.HR_ERR_INVALID_ARG
