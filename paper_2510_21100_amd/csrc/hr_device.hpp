@@ -2013,18 +2013,52 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
             for (int w = 0; w < CK; ++w) acc[w] = fma(l, r[w + 1] - r[w], acc[w]);
           }
         }
-        double* part = reinterpret_cast<double*>(sm.spare);  // CK x NT lane partials
-        static_assert(LIST || sizeof(sm.spare) >= CK * NT * sizeof(double), "spare holds the class partials");
+        // The group's lanes [f, f + g) add up: a segmented scan inside each
+        // wave the group spans gives one piece per wave, kept at index
+        // q + (wave of the lane) (unique: groups are consecutive); the
+        // group's first lane adds its pieces in wave order.
+        double* piece = reinterpret_cast<double*>(sm.spare);  // [P + NT / 64][CK]
+        static_assert(LIST || sizeof(sm.spare) >= (BINS / CK + NT / 64) * CK * sizeof(double),
+                      "spare holds the class pieces");
+        {
+          const int f = t - cl.k, wv = t >> 6;
+          const int seg0 = cl.q >= 0 ? max(f - (t & ~63), 0) : lane;
 #pragma unroll
-        for (int w = 0; w < CK; ++w) part[w * NT + t] = acc[w];
-        __syncthreads();
-        if (cl.q >= 0 && cl.k == 0) {
           for (int w = 0; w < CK; ++w) {
-            const int m = CK * cl.q + w;
-            if (m >= BINS || sm.PA[m + 1] == sm.PA[m]) continue;  // only the classes of A
-            double d = 0.0;
-            for (int x = 0; x < cl.g; ++x) d += part[w * NT + t + x];
-            sm.rho[m] = d > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d) : 0.f;
+            double x = acc[w], y;
+            y = dpp_get<dpp::ROW_SHR + 1, 0xf>(x);
+            if (lane - 1 >= seg0) x += y;
+            y = dpp_get<dpp::ROW_SHR + 2, 0xf>(x);
+            if (lane - 2 >= seg0) x += y;
+            y = dpp_get<dpp::ROW_SHR + 4, 0xf>(x);
+            if (lane - 4 >= seg0) x += y;
+            y = dpp_get<dpp::ROW_SHR + 8, 0xf>(x);
+            if (lane - 8 >= seg0) x += y;
+            y = dpp_get<dpp::BCAST15, 0xa>(x);
+            if ((lane & ~15) - 1 >= seg0) x += y;
+            y = dpp_get<dpp::BCAST31, 0xc>(x);
+            if (31 >= seg0) x += y;
+            acc[w] = x;
+          }
+          if (cl.q >= 0 && (lane == 63 || cl.k == cl.g - 1)) {
+#pragma unroll
+            for (int w = 0; w < CK; ++w) piece[(cl.q + wv) * CK + w] = acc[w];
+          }
+          __syncthreads();
+          if (cl.q >= 0 && cl.k == 0) {
+            const int w0 = f >> 6, w1 = (f + cl.g - 1) >> 6;
+            double d[CK];
+#pragma unroll
+            for (int w = 0; w < CK; ++w) d[w] = piece[(cl.q + w0) * CK + w];
+            for (int v = w0 + 1; v <= w1; ++v)
+#pragma unroll
+              for (int w = 0; w < CK; ++w) d[w] += piece[(cl.q + v) * CK + w];
+#pragma unroll
+            for (int w = 0; w < CK; ++w) {
+              const int m = CK * cl.q + w;
+              if (m >= BINS || sm.PA[m + 1] == sm.PA[m]) continue;  // only the classes of A
+              sm.rho[m] = d[w] > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d[w]) : 0.f;
+            }
           }
         }
       }
