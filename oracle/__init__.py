@@ -6,6 +6,10 @@ calls it, and it shares no code with the GPU library.
 """
 
 from .histretinex import (  # noqa: F401
+    GRAD_OPERATORS,
+    GRAD_RESCALES,
+    UPDATES,
+    INIT_L,
     Params,
     value_channel,
     count_histogram,

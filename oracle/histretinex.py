@@ -48,11 +48,26 @@ from dataclasses import dataclass
 import numpy as np
 
 
+#: gradient operators for H_C(grad S) (the paper does not define the operator)
+GRAD_OPERATORS = ("fwd_l1", "fwd_l2", "sobel_l1")
+#: how the raw gradient levels are put onto the l image levels
+GRAD_RESCALES = ("max", "clip")
+#: readings of Eqs. (12)-(13): multiply by K (stationarity of Eq. 10) or the
+#: printed division by K
+UPDATES = ("mul", "div")
+#: initial illumination histogram: the image histogram, or uniform over all levels
+INIT_L = ("image", "uniform")
+
+
 @dataclass(frozen=True)
 class Params:
     """Method parameters: bins l, iterations T (the maximum of Alg. 1), prior
     weights alpha, beta of Eq. (10), the illumination gamma of Eq. (17) and
-    the error threshold eps of Alg. 1 (<= 0: exactly T passes)."""
+    the error threshold eps of Alg. 1 (<= 0: exactly T passes).  The last
+    four fields switch between readings of passages the paper leaves open
+    (the defaults are the readings the pipeline is built on): the gradient
+    operator and the rescaling of its histogram, the form of Eqs. (12)-(13),
+    and the initial illumination histogram."""
 
     bins: int = 256
     iters: int = 50
@@ -60,6 +75,20 @@ class Params:
     beta: float = 0.01
     gamma: float = 2.2
     eps: float = 0.0
+    grad_op: str = "fwd_l1"
+    grad_rescale: str = "max"
+    update: str = "mul"
+    init_l: str = "image"
+
+    def __post_init__(self):
+        if self.grad_op not in GRAD_OPERATORS:
+            raise ValueError(f"grad_op must be one of {GRAD_OPERATORS}")
+        if self.grad_rescale not in GRAD_RESCALES:
+            raise ValueError(f"grad_rescale must be one of {GRAD_RESCALES}")
+        if self.update not in UPDATES:
+            raise ValueError(f"update must be one of {UPDATES}")
+        if self.init_l not in INIT_L:
+            raise ValueError(f"init_l must be one of {INIT_L}")
 
 
 # --------------------------------------------------------------------------
@@ -81,31 +110,67 @@ def count_histogram(values: np.ndarray, levels: int) -> np.ndarray:
     return np.bincount(v, minlength=levels).astype(np.int64)
 
 
-def gradient_magnitude(V: np.ndarray) -> np.ndarray:
+def _round_sqrt(q: np.ndarray) -> np.ndarray:
+    """round-half-up(sqrt(q)) of non-negative integers, exactly: r = isqrt(q),
+    plus one when q - r^2 > r (sqrt(q) >= r + 1/2 iff q >= r^2 + r + 1/4)."""
+    q = np.asarray(q, dtype=np.int64)
+    r = np.floor(np.sqrt(q.astype(np.float64))).astype(np.int64)
+    r -= (r * r > q)          # isqrt: correct the float estimate downwards
+    r += ((r + 1) * (r + 1) <= q)  # and upwards
+    return r + (q - r * r > r)
+
+
+def gradient_magnitude(V: np.ndarray, operator: str = "fwd_l1") -> np.ndarray:
     """Gradient image of the value channel (Alg. 1 initialisation; the operator
-    is not given in the paper): forward differences, L1 magnitude, the last
-    column and row replicated so their missing difference is 0."""
+    is not given in the paper), integer levels in [0, 2(l-1)]:
+
+      fwd_l1   forward differences, |dx| + |dy|, the last column and row
+               replicated so their missing difference is 0 (the default);
+      fwd_l2   the same differences, Euclidean magnitude sqrt(dx^2 + dy^2)
+               rounded half up;
+      sobel_l1 the 3x3 Sobel derivatives gx, gy on the image with its border
+               replicated, (|gx| + |gy|) / 4 rounded half up (the Sobel
+               weights sum to 4, so a step of height h gives h).
+    """
     V = np.asarray(V, dtype=np.int64)
-    dx = np.zeros_like(V)
-    dy = np.zeros_like(V)
-    dx[:, :-1] = np.abs(V[:, 1:] - V[:, :-1])
-    dy[:-1, :] = np.abs(V[1:, :] - V[:-1, :])
-    return dx + dy
+    if operator in ("fwd_l1", "fwd_l2"):
+        dx = np.zeros_like(V)
+        dy = np.zeros_like(V)
+        dx[:, :-1] = V[:, 1:] - V[:, :-1]
+        dy[:-1, :] = V[1:, :] - V[:-1, :]
+        if operator == "fwd_l1":
+            return np.abs(dx) + np.abs(dy)
+        return _round_sqrt(dx * dx + dy * dy)
+    if operator == "sobel_l1":
+        P = np.pad(V, 1, mode="edge")
+        H, W = V.shape
+        n = lambda dy, dx: P[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]  # noqa: E731
+        gx = (n(-1, 1) + 2 * n(0, 1) + n(1, 1)) - (n(-1, -1) + 2 * n(0, -1) + n(1, -1))
+        gy = (n(1, -1) + 2 * n(1, 0) + n(1, 1)) - (n(-1, -1) + 2 * n(-1, 0) + n(-1, 1))
+        return (np.abs(gx) + np.abs(gy) + 2) // 4
+    raise ValueError(f"unknown gradient operator {operator!r}")
 
 
-def gradient_histogram(V: np.ndarray, levels: int):
+def gradient_histogram(V: np.ndarray, levels: int, operator: str = "fwd_l1", rescale: str = "max"):
     """H_C(grad S) on the l image levels (Alg. 1 initialisation).
 
     Returns (raw, gmax, hist): raw is the 2l-1 level histogram of the gradient
-    image, gmax its largest occupied level, and hist the l-level histogram
-    obtained by mapping raw level j to round-half-up(j * (l-1) / gmax)
-    (everything to level 0 when gmax = 0).  The total count stays N.
+    image, gmax its largest occupied level, and hist the l-level histogram.
+    With rescale "max" (the default) raw level j goes to
+    round-half-up(j * (l-1) / gmax) (everything to level 0 when gmax = 0);
+    with "clip" it goes to min(j, l-1).  The total count stays N.
     """
-    g = gradient_magnitude(V)
+    g = gradient_magnitude(V, operator)
     raw = count_histogram(g, 2 * levels - 1)
     occupied = np.nonzero(raw)[0]
     gmax = int(occupied.max()) if occupied.size else 0
     hist = np.zeros(levels, dtype=np.int64)
+    if rescale == "clip":
+        for j in range(2 * levels - 1):
+            hist[min(j, levels - 1)] += raw[j]
+        return raw, gmax, hist
+    if rescale != "max":
+        raise ValueError(f"unknown rescale {rescale!r}")
     if gmax == 0:
         hist[0] = raw.sum()
         return raw, gmax, hist
@@ -177,9 +242,10 @@ def classify_enhanced(levels: int, gamma: float) -> np.ndarray:
 # Histogram-domain Retinex optimisation (Eqs. 6, 8, 10-15; Alg. 1)
 # --------------------------------------------------------------------------
 
-def init_state(hS: np.ndarray, hG: np.ndarray):
+def init_state(hS: np.ndarray, hG: np.ndarray, init_l: str = "image"):
     """Alg. 1 initialisation in probability units: s = H_C(S)/N,
-    g = H_C(grad S)/N, R^(0) = g and (our reading) L^(0) = s."""
+    g = H_C(grad S)/N, R^(0) = g and (our reading) L^(0) = s, or with
+    init_l "uniform" L^(0) = 1/l on every level."""
     hS = np.asarray(hS, dtype=np.float64)
     hG = np.asarray(hG, dtype=np.float64)
     N = hS.sum()
@@ -187,6 +253,10 @@ def init_state(hS: np.ndarray, hG: np.ndarray):
         raise ValueError("histograms must be non-empty and of equal mass")
     s = hS / N
     g = hG / N
+    if init_l == "uniform":
+        return s, g, np.full(s.size, 1.0 / s.size), g.copy()
+    if init_l != "image":
+        raise ValueError(f"unknown init_l {init_l!r}")
     return s, g, s.copy(), g.copy()
 
 
@@ -213,21 +283,31 @@ def objective(lv, rv, K, s, g, idx, alpha, beta) -> float:
                  + beta * ((rv - g) ** 2).sum())
 
 
-def update_step(lv, rv, s, g, idx, alpha, beta, K=None):
+def update_step(lv, rv, s, g, idx, alpha, beta, K=None, update: str = "mul"):
     """One pass of the Alg. 1 loop.
 
     R is updated by Eq. (13) with the current L and K, L by Eq. (12) with the
     new (unnormalised) R and the same K, then both are rescaled to unit mass
-    (Eqs. 15, 14).  Returns a dict with the unnormalised and normalised
-    iterates and the K that was used.
+    (Eqs. 15, 14).  With update "mul" (our reading) the sums weight S_index by
+    K; with "div" they divide by K as printed, cells with K = 0 (an empty
+    level of L or R, or an empty class) contributing nothing.  Returns a dict
+    with the unnormalised and normalised iterates and the K that was used.
     """
     if K is None:
         _, _, K = weights(lv, rv, idx)
     S_idx = s[idx]
+    if update == "mul":
+        W = K
+    elif update == "div":
+        W = np.zeros_like(K)
+        pos = K > 0
+        W[pos] = 1.0 / K[pos]
+    else:
+        raise ValueError(f"unknown update {update!r}")
     # Eq. (13): R_b = (sum_a L_a K_ab S_index(a,b) + beta G_b) / (sum_a L_a^2 + beta)
-    r_new = ((lv[:, None] * K * S_idx).sum(axis=0) + beta * g) / ((lv ** 2).sum() + beta)
+    r_new = ((lv[:, None] * W * S_idx).sum(axis=0) + beta * g) / ((lv ** 2).sum() + beta)
     # Eq. (12): L_a = (sum_b R_b K_ab S_index(a,b) + alpha S_a) / (sum_b R_b^2 + alpha)
-    l_new = ((r_new[None, :] * K * S_idx).sum(axis=1) + alpha * s) / ((r_new ** 2).sum() + alpha)
+    l_new = ((r_new[None, :] * W * S_idx).sum(axis=1) + alpha * s) / ((r_new ** 2).sum() + alpha)
     return {
         "K": K,
         "r_unnorm": r_new,
@@ -251,14 +331,14 @@ def solve(hS, hG, params: Params, record: bool = False):
     """
     levels = int(params.bins)
     idx = classify(levels)
-    s, g, lv, rv = init_state(hS, hG)
+    s, g, lv, rv = init_state(hS, hG, params.init_l)
     eps = float(params.eps)
     info = {"J_before": [], "J_after_r": [], "J_after_l": [], "residual": [], "change_l": [], "change_r": []}
     margin = np.inf
     passes = 0
     _, _, K = weights(lv, rv, idx)
     for _ in range(int(params.iters)):
-        step = update_step(lv, rv, s, g, idx, params.alpha, params.beta, K=K)
+        step = update_step(lv, rv, s, g, idx, params.alpha, params.beta, K=K, update=params.update)
         if record:
             info["J_before"].append(objective(lv, rv, K, s, g, idx, params.alpha, params.beta))
             info["J_after_r"].append(objective(lv, step["r_unnorm"], K, s, g, idx,
@@ -381,7 +461,7 @@ def enhance(img: np.ndarray, params: Params = Params(), record: bool = False):
         raise ValueError("pixel value exceeds the level range")
     npix = V.size
     hS = count_histogram(V, levels)
-    graw, gmax, hG = gradient_histogram(V, levels)
+    graw, gmax, hG = gradient_histogram(V, levels, params.grad_op, params.grad_rescale)
     lv, rv, info = solve(hS, hG, params, record=record)
     target = target_histogram(lv, rv, npix, params.gamma)
     lut, margin = matching_lut(hS, target)
