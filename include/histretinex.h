@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define HR_ABI_VERSION 2
+#define HR_ABI_VERSION 3
 
 typedef enum {
   HR_OK = 0,
@@ -78,7 +78,11 @@ typedef struct {
  *            runs exactly iters passes.  The changes are summed in FP32, so
  *            an image whose change in some pass lies within FP32 rounding of
  *            eps may stop one pass away from an FP64 evaluation.
- *  variant : must be 0 (reserved for variants of the method's readings) */
+ *  variant : 0, or HR_VARIANT_* bits selecting other readings of passages
+ *            the paper leaves open (below); only the one-image calls take
+ *            them: hr_solve the solver bits (the gradient bits belong to
+ *            hr_build_hist_variant), the batched and differentiated calls
+ *            none (HR_ERR_UNSUPPORTED) */
 typedef struct {
   int32_t bins;
   int32_t iters;
@@ -89,6 +93,29 @@ typedef struct {
   uint32_t variant;
   int32_t reserved; /* must be 0 */
 } hr_params;
+
+/* Variant readings (hr_params.variant, hr_build_hist_variant's variant).
+ * The main path reads the paper as: forward-difference L1 gradient,
+ * histogram rescaled so its largest occupied raw level lands on l-1,
+ * Eqs. (12)-(13) multiplying by K (the stationarity conditions of Eq. 10),
+ * L(0) = the image histogram.  The variants run through simple kernels (one
+ * thread per pixel, a dense solver over all l levels), not the tuned path.
+ *  HR_VARIANT_GRAD_L2      gradient sqrt(dx^2 + dy^2) of the forward
+ *                          differences, rounded half up
+ *  HR_VARIANT_GRAD_SOBEL   3x3 Sobel derivatives on the border-replicated
+ *                          image, (|gx| + |gy|) / 4 rounded half up
+ *                          (excludes HR_VARIANT_GRAD_L2)
+ *  HR_VARIANT_GRAD_CLIP    raw gradient level j goes to min(j, l-1) instead
+ *                          of being rescaled by the largest occupied level
+ *  HR_VARIANT_UPDATE_DIV   Eqs. (12)-(13) as printed, dividing by K_ij;
+ *                          cells with K = 0 (an empty level of L or R, an
+ *                          empty class) contribute nothing
+ *  HR_VARIANT_INIT_UNIFORM L(0) = 1/l on every level */
+#define HR_VARIANT_GRAD_L2 0x1u
+#define HR_VARIANT_GRAD_SOBEL 0x2u
+#define HR_VARIANT_GRAD_CLIP 0x4u
+#define HR_VARIANT_UPDATE_DIV 0x8u
+#define HR_VARIANT_INIT_UNIFORM 0x10u
 
 /* Launch schedule of the batched form (chosen by the autotuner).  A step is
  * one pass of the persistent workgroup over its pixels: 1024 threads x 8 px
@@ -133,6 +160,13 @@ hr_status hr_get_flags(hr_workspace* ws, uint32_t* flags, int32_t clear);
 hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
                         uint32_t* hist_grad_raw, hr_workspace* ws, void* stream);
 
+/* hr_build_hist with another gradient operator or rescaling: variant holds
+ * HR_VARIANT_GRAD_* bits only (any other bit: HR_ERR_INVALID_ARG); 0 is
+ * hr_build_hist itself.  hist_v is the same value histogram; hist_grad and
+ * hist_grad_raw follow the selected operator (raw levels 0..2(l-1)). */
+hr_status hr_build_hist_variant(const hr_image* img, int32_t bits, uint32_t variant, uint32_t* hist_v,
+                                uint32_t* hist_grad, uint32_t* hist_grad_raw, hr_workspace* ws, void* stream);
+
 /* The histograms of hr_build_hist for n images of one bit depth, in one
  * launch (a grid of tiles per image; the last tile of an image rescales its
  * gradient histogram).
@@ -160,7 +194,9 @@ hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint3
  * the device: a mass of hist_v other than npix, or of hist_grad other than
  * that of hist_v, sets HR_FLAG_HIST_MASS (read with hr_get_flags) and the
  * histograms are used as given; histograms without any mass give zero
- * outputs. */
+ * outputs.  With HR_VARIANT_UPDATE_DIV or HR_VARIANT_INIT_UNIFORM in
+ * p->variant the dense variant solver runs instead (all l levels, FP32
+ * state with FP64 sums; much slower). */
 hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t npix,
                    const hr_params* p, float* illum, float* refl, float* target, int32_t* passes,
                    hr_workspace* ws, void* stream);

@@ -21,11 +21,19 @@ HR_ERR_DEVICE = 4
 HR_FLAG_VALUE_CLAMPED = 0x1
 HR_FLAG_HIST_MASS = 0x2
 HR_NOALLOC_MAX_IMAGES = 4
+HR_VARIANT_GRAD_L2 = 0x1
+HR_VARIANT_GRAD_SOBEL = 0x2
+HR_VARIANT_GRAD_CLIP = 0x4
+HR_VARIANT_UPDATE_DIV = 0x8
+HR_VARIANT_INIT_UNIFORM = 0x10
+HR_VARIANT_GRAD_BITS = 0x7
+HR_VARIANT_SOLVE_BITS = 0x18
 
 #: every symbol the header declares
 EXPORTS = (
     "hr_workspace_create", "hr_workspace_destroy", "hr_workspace_set_schedule", "hr_get_flags",
-    "hr_build_hist", "hr_build_hist_batch", "hr_solve", "hr_match", "hr_equalize", "hr_enhance_batch",
+    "hr_build_hist", "hr_build_hist_variant", "hr_build_hist_batch", "hr_solve", "hr_match", "hr_equalize",
+    "hr_enhance_batch",
     "hr_enhance_batch_noalloc",
     "hr_solve_ckpt", "hr_softmatch_loss_grad", "hr_solve_vjp",
     "hr_status_string", "hr_last_error", "hr_abi_version",
@@ -65,6 +73,7 @@ def _load():
         "hr_workspace_set_schedule": (C.c_int, [P, C.POINTER(HrSchedule)]),
         "hr_get_flags": (C.c_int, [P, u32p, C.c_int32]),
         "hr_build_hist": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, P, P, P]),
+        "hr_build_hist_variant": (C.c_int, [C.POINTER(HrImage), C.c_int32, C.c_uint32, P, P, P, P, P]),
         "hr_build_hist_batch": (C.c_int, [C.POINTER(HrImage), C.c_int32, C.c_int32, P, P, P, P]),
         "hr_solve": (C.c_int, [P, P, C.c_int64, C.POINTER(HrParams), P, P, P, P, P, P]),
         "hr_match": (C.c_int, [C.POINTER(HrImage), C.c_int32, P, P, P, C.c_int64, P, P, P]),

@@ -21,9 +21,9 @@ from ._lib import HrImage, HrParams, HrSchedule, check, lib
 @dataclass(frozen=True)
 class Params:
     """bins l, the maximum number of passes T, prior weights alpha, beta
-    (Eq. 10), gamma (Eq. 17) and the stopping threshold eps of Alg. 1 (the
+    (Eq. 10), gamma (Eq. 17), the stopping threshold eps of Alg. 1 (the
     squared change of both normalised histograms in a pass; <= 0: exactly T
-    passes)."""
+    passes) and the HR_VARIANT_* bits of other readings (0: the main path)."""
 
     bins: int = 256
     iters: int = 50
@@ -31,9 +31,11 @@ class Params:
     beta: float = 0.01
     gamma: float = 2.2
     eps: float = 0.0
+    variant: int = 0
 
-    def c(self) -> HrParams:
-        return HrParams(self.bins, self.iters, self.alpha, self.beta, self.gamma, self.eps, 0, 0)
+    def c(self, variant: int | None = None) -> HrParams:
+        v = self.variant if variant is None else variant
+        return HrParams(self.bins, self.iters, self.alpha, self.beta, self.gamma, self.eps, v, 0)
 
 
 def _bits_of(img: torch.Tensor) -> int:
@@ -111,8 +113,10 @@ def workspace(max_images: int = 1, max_bins: int = 1024) -> Workspace:
     return ws
 
 
-def build_hist(img: torch.Tensor, ws: Workspace | None = None):
-    """Returns (hist_v, hist_grad, hist_grad_raw) as int32 tensors (counts)."""
+def build_hist(img: torch.Tensor, ws: Workspace | None = None, variant: int = 0):
+    """Returns (hist_v, hist_grad, hist_grad_raw) as int32 tensors (counts).
+    ``variant``: HR_VARIANT_GRAD_* bits (another gradient operator or
+    rescaling, through hr_build_hist_variant)."""
     bits = _bits_of(img)
     bins = 1 << bits
     ws = ws or workspace()
@@ -121,7 +125,12 @@ def build_hist(img: torch.Tensor, ws: Workspace | None = None):
     hg = torch.empty(bins, dtype=torch.int32, device=dev)
     hraw = torch.empty(2 * bins - 1, dtype=torch.int32, device=dev)
     d = _image(img)
-    check(lib.hr_build_hist(C.byref(d), bits, hv.data_ptr(), hg.data_ptr(), hraw.data_ptr(), ws.handle, _stream()))
+    if variant:
+        check(lib.hr_build_hist_variant(C.byref(d), bits, variant, hv.data_ptr(), hg.data_ptr(), hraw.data_ptr(),
+                                        ws.handle, _stream()))
+    else:
+        check(lib.hr_build_hist(C.byref(d), bits, hv.data_ptr(), hg.data_ptr(), hraw.data_ptr(), ws.handle,
+                                _stream()))
     return hv, hg, hraw
 
 
@@ -165,7 +174,7 @@ def solve(hist_v: torch.Tensor, hist_grad: torch.Tensor, npix: int, params: Para
         if passes.dtype != torch.int32 or passes.numel() < 1:
             raise ValueError("passes must be an int32 tensor with at least one element")
         pp = _on_gpu(passes, "passes").data_ptr()
-    p = params.c()
+    p = params.c(params.variant & _lib.HR_VARIANT_SOLVE_BITS)
     check(lib.hr_solve(hist_v.contiguous().data_ptr(), hist_grad.contiguous().data_ptr(), int(npix), C.byref(p),
                        illum.data_ptr(), refl.data_ptr(), target.data_ptr(), pp, ws.handle, _stream()))
     return illum, refl, target
@@ -226,7 +235,7 @@ def enhance(img: torch.Tensor, params: Params | None = None, ws: Workspace | Non
     params = params or Params(bins=1 << bits)
     if params.bins != 1 << bits:
         raise ValueError("params.bins must equal 2^bits of the image")
-    hv, hg, hraw = build_hist(img, ws)
+    hv, hg, hraw = build_hist(img, ws, params.variant & _lib.HR_VARIANT_GRAD_BITS)
     npix = img.shape[0] * img.shape[1]
     passes = torch.empty(1, dtype=torch.int32, device=img.device)
     illum, refl, target = solve(hv, hg, npix, params, ws, passes=passes)

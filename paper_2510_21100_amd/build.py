@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhistretinex.so")
-SOURCES = ["hr_kernels.hip", "hr_diff.hip", "hr_abi.cpp"]
+SOURCES = ["hr_kernels.hip", "hr_diff.hip", "hr_variant.hip", "hr_abi.cpp"]
 HEADERS = ["hr_device.hpp", "hr_launch.hpp"]
 
 

@@ -165,8 +165,19 @@ hr_status check_params(const hr_params* p, int bits) {
   if (!(std::isfinite(p->beta) && p->beta > 0)) return fail(HR_ERR_INVALID_ARG, "beta must be finite and > 0");
   if (!(std::isfinite(p->gamma) && p->gamma > 0)) return fail(HR_ERR_INVALID_ARG, "gamma must be finite and > 0");
   if (!std::isfinite(p->eps)) return fail(HR_ERR_INVALID_ARG, "eps must be finite");
-  if (p->variant != 0) return fail(HR_ERR_UNSUPPORTED, "unknown variant bits");
+  if (p->variant & ~(hr::VARIANT_GRAD_BITS | hr::VARIANT_SOLVE_BITS))
+    return fail(HR_ERR_UNSUPPORTED, "unknown variant bits");
+  if ((p->variant & hr::VARIANT_GRAD_L2) && (p->variant & hr::VARIANT_GRAD_SOBEL))
+    return fail(HR_ERR_INVALID_ARG, "HR_VARIANT_GRAD_L2 and HR_VARIANT_GRAD_SOBEL exclude each other");
   if (p->reserved != 0) return fail(HR_ERR_INVALID_ARG, "reserved field must be 0");
+  return HR_OK;
+}
+
+// The batched and differentiated calls run the main path's readings only.
+hr_status check_no_variant(const hr_params* p, const char* what) {
+  if (p->variant != 0)
+    return fail(HR_ERR_UNSUPPORTED, std::string(what) + ": variant readings run through the one-image calls "
+                                                        "(hr_build_hist_variant, hr_solve)");
   return HR_OK;
 }
 
@@ -177,6 +188,7 @@ hr::SolveParams solve_params(const hr_params* p) {
   sp.beta = (float)p->beta;
   sp.inv_gamma = 1.0 / p->gamma;
   sp.eps = p->eps > 0 ? (float)p->eps : 0.f;
+  sp.variant = p->variant & hr::VARIANT_SOLVE_BITS;
   return sp;
 }
 
@@ -302,6 +314,30 @@ hr_status hr_build_hist(const hr_image* img, int32_t bits, uint32_t* hist_v, uin
   return HR_OK;
 }
 
+hr_status hr_build_hist_variant(const hr_image* img, int32_t bits, uint32_t variant, uint32_t* hist_v,
+                                uint32_t* hist_grad, uint32_t* hist_grad_raw, hr_workspace* ws, void* stream) {
+  if (variant & ~hr::VARIANT_GRAD_BITS)
+    return fail(HR_ERR_INVALID_ARG, "hr_build_hist_variant: only gradient variant bits belong here");
+  if ((variant & hr::VARIANT_GRAD_L2) && (variant & hr::VARIANT_GRAD_SOBEL))
+    return fail(HR_ERR_INVALID_ARG, "HR_VARIANT_GRAD_L2 and HR_VARIANT_GRAD_SOBEL exclude each other");
+  if (variant == 0) return hr_build_hist(img, bits, hist_v, hist_grad, hist_grad_raw, ws, stream);
+  hr_status st = check_bits(bits);
+  if (st) return st;
+  const int bins = 1 << bits;
+  hr::ImgDesc d;
+  if ((st = make_desc(img, bits, "hr_build_hist_variant", &d))) return st;
+  if (!hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_build_hist_variant: histogram pointer is NULL");
+  if ((st = check_ws(ws, bins))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* graw = hist_grad_raw ? hist_grad_raw : ws->d_graw;
+  HR_HIP(hr::launch::fill_u32(hist_v, bins, 0, s));
+  HR_HIP(hr::launch::fill_u32(graw, 2 * bins - 1, 0, s));
+  constexpr int64_t kVariantTilePx = 256 * 16;
+  HR_HIP(hr::launch::hist_variant(bits, d, kVariantTilePx, variant, hist_v, graw, hist_grad, ws->d_flags + 1,
+                                  ws->d_flags, s));
+  return HR_OK;
+}
+
 hr_status hr_build_hist_batch(const hr_image* in, int32_t n, int32_t bits, uint32_t* hist_v, uint32_t* hist_grad,
                               hr_workspace* ws, void* stream) {
   hr_status st = check_bits(bits);
@@ -348,8 +384,15 @@ hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t np
   if (!hist_v || !hist_grad) return fail(HR_ERR_INVALID_ARG, "hr_solve: histogram pointer is NULL");
   if (!illum || !refl || !target) return fail(HR_ERR_INVALID_ARG, "hr_solve: output pointer is NULL");
   if (npix <= 0 || npix >= (1LL << 32) - 1) return fail(HR_ERR_INVALID_ARG, "hr_solve: npix out of range");
+  if (p->variant & hr::VARIANT_GRAD_BITS)
+    return fail(HR_ERR_INVALID_ARG, "hr_solve: gradient variant bits belong to hr_build_hist_variant");
   if ((st = check_ws(ws, p->bins))) return st;
   const hr::SolveParams sp = solve_params(p);
+  if (sp.variant) {
+    HR_HIP(hr::launch::solve_variant(p->bins, hist_v, hist_grad, npix, sp, illum, refl, target, passes, ws->d_flags,
+                                     static_cast<hipStream_t>(stream)));
+    return HR_OK;
+  }
   HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, ws->d_lists, illum, refl, target, passes,
                            ws->d_flags, static_cast<hipStream_t>(stream)));
   return HR_OK;
@@ -395,6 +438,7 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   hr_status st = check_bits(bits);
   if (st) return st;
   if ((st = check_params(p, bits))) return st;
+  if ((st = check_no_variant(p, "hr_enhance_batch"))) return st;
   const int bins = 1 << bits;
   if (!in || !out || !out_row_stride_bytes) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch: NULL array");
   if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch: n must be >= 1");
@@ -490,6 +534,7 @@ hr_status hr_enhance_batch_noalloc(const hr_image* in, void* const* out, const i
   hr_status st = check_bits(bits);
   if (st) return st;
   if ((st = check_params(p, bits))) return st;
+  if ((st = check_no_variant(p, "hr_enhance_batch_noalloc"))) return st;
   if (!in || !out || !out_row_stride_bytes) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch_noalloc: NULL array");
   if (n < 1) return fail(HR_ERR_INVALID_ARG, "hr_enhance_batch_noalloc: n must be >= 1");
   if (n > hr::NOALLOC_MAX_IMAGES)
@@ -532,6 +577,7 @@ hr_status hr_enhance_batch_noalloc(const hr_image* in, void* const* out, const i
 static hr_status check_diff(const hr_params* p, int32_t n, int32_t ckpt_every, const char* what) {
   hr_status st = check_params(p, 8);
   if (st) return st;
+  if ((st = check_no_variant(p, what))) return st;
   if (p->eps > 0)
     return fail(HR_ERR_UNSUPPORTED, std::string(what) + ": the differentiated form runs exactly iters passes (eps <= 0)");
   if (n < 1) return fail(HR_ERR_INVALID_ARG, std::string(what) + ": n must be >= 1");

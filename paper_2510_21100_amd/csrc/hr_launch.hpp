@@ -33,8 +33,19 @@ struct SolveParams {
   int32_t ckpt_every;  // differentiated form: checkpoint interval (0: none)
   double inv_gamma;
   float eps;           // stopping threshold of Alg. 1 (<= 0: exactly iters passes)
-  int32_t pad;
+  uint32_t variant;    // VARIANT_* bits of the solver (0: the main path's readings)
 };
+
+// Variant readings (the bits of hr_params.variant): the gradient operator and
+// the rescaling of its histogram (histogram calls), the form of Eqs. (12)-(13)
+// and the initial illumination histogram (solver calls).
+constexpr uint32_t VARIANT_GRAD_L2 = 0x1u;
+constexpr uint32_t VARIANT_GRAD_SOBEL = 0x2u;
+constexpr uint32_t VARIANT_GRAD_CLIP = 0x4u;
+constexpr uint32_t VARIANT_UPDATE_DIV = 0x8u;
+constexpr uint32_t VARIANT_INIT_UNIFORM = 0x10u;
+constexpr uint32_t VARIANT_GRAD_BITS = VARIANT_GRAD_L2 | VARIANT_GRAD_SOBEL | VARIANT_GRAD_CLIP;
+constexpr uint32_t VARIANT_SOLVE_BITS = VARIANT_UPDATE_DIV | VARIANT_INIT_UNIFORM;
 
 // Optional per-image outputs of the batched form, indexed by the caller's slot.
 struct BatchOut {
@@ -124,6 +135,11 @@ hipError_t softmatch(int n, const ImgDesc* desc, int64_t max_npix, const uint32_
 hipError_t solve_vjp(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, const float* ckpt,
                      const float* dtarget, double* dalpha, double* dbeta, uint32_t* flags, hipStream_t s);
 int diff_seg_max();
+// variant readings (hr_variant.hip)
+hipError_t hist_variant(int bits, const ImgDesc& d, int64_t tile_px, uint32_t variant, uint32_t* hs, uint32_t* graw,
+                        uint32_t* hg, uint32_t* ticket, uint32_t* flags, hipStream_t s);
+hipError_t solve_variant(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
+                         float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags, hipStream_t s);
 // The batched kernel on the library's own fixed scratch (no allocation): t
 // holds the header and the n descriptors in queue order; flags_user (device,
 // may be NULL) receives the sticky flags.  Calls on one GPU share the scratch.

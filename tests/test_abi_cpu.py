@@ -112,7 +112,13 @@ def test_solve_validation(L):
     assert _solve(L, _params(L, gamma=float("nan"))) == L.HR_ERR_INVALID_ARG
     assert _solve(L, _params(L, alpha=float("inf"))) == L.HR_ERR_INVALID_ARG
     assert _solve(L, _params(L, eps=float("nan"))) == L.HR_ERR_INVALID_ARG
-    assert _solve(L, _params(L, variant=1)) == L.HR_ERR_UNSUPPORTED
+    assert _solve(L, _params(L, variant=0x20)) == L.HR_ERR_UNSUPPORTED  # unknown bit
+    assert _solve(L, _params(L, variant=L.HR_VARIANT_GRAD_L2)) == L.HR_ERR_INVALID_ARG
+    assert "gradient" in _err(L)
+    assert _solve(L, _params(L, variant=L.HR_VARIANT_GRAD_L2 | L.HR_VARIANT_GRAD_SOBEL)) == L.HR_ERR_INVALID_ARG
+    for v in (L.HR_VARIANT_UPDATE_DIV, L.HR_VARIANT_INIT_UNIFORM, L.HR_VARIANT_SOLVE_BITS):
+        assert _solve(L, _params(L, variant=v)) == L.HR_ERR_INVALID_ARG  # valid: stops at the missing workspace
+        assert "workspace" in _err(L)
     assert _solve(L, _params(L, reserved=3)) == L.HR_ERR_INVALID_ARG
     assert L.lib.hr_solve(0x2000, 0x3000, 100, None, 0x4000, 0x5000, 0x6000, None, None, None) == L.HR_ERR_INVALID_ARG
     p = _params(L)
@@ -163,6 +169,30 @@ def test_enhance_batch_validation(L):
     assert f(imgs, outs, bad, n, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
     assert f(imgs, outs, strides, n, 8, C.byref(p), None, None, None, None, None, None, None) == L.HR_ERR_INVALID_ARG
     assert "workspace" in _err(L)
+
+
+def test_variant_calls_validation(L):
+    """hr_build_hist_variant takes gradient bits only; the batched and
+    differentiated calls take no variant bits."""
+    f = L.lib.hr_build_hist_variant
+    img = _img()
+    assert f(C.byref(img), 8, L.HR_VARIANT_UPDATE_DIV, 0x2000, 0x3000, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 8, L.HR_VARIANT_GRAD_L2 | L.HR_VARIANT_GRAD_SOBEL, 0x2000, 0x3000, None, None, None) \
+        == L.HR_ERR_INVALID_ARG
+    assert f(None, 8, L.HR_VARIANT_GRAD_SOBEL, 0x2000, 0x3000, None, None, None) == L.HR_ERR_INVALID_ARG
+    assert f(C.byref(img), 9, L.HR_VARIANT_GRAD_SOBEL, 0x2000, 0x3000, None, None, None) == L.HR_ERR_UNSUPPORTED
+    for v in (L.HR_VARIANT_GRAD_L2, L.HR_VARIANT_GRAD_SOBEL | L.HR_VARIANT_GRAD_CLIP, 0):
+        assert f(C.byref(img), 8, v, 0x2000, 0x3000, None, None, None) == L.HR_ERR_INVALID_ARG
+        assert "workspace" in _err(L)
+    n = 1
+    imgs = (L.HrImage * n)(_img())
+    outs = (C.c_void_p * n)(0x8000)
+    strides = (C.c_int64 * n)(3 * 64)
+    p = _params(L, variant=L.HR_VARIANT_UPDATE_DIV)
+    args = (None, None, None, None, None, None, None)
+    assert L.lib.hr_enhance_batch(imgs, outs, strides, n, 8, C.byref(p), *args) == L.HR_ERR_UNSUPPORTED
+    assert L.lib.hr_enhance_batch_noalloc(imgs, outs, strides, n, 8, C.byref(p), *args) == L.HR_ERR_UNSUPPORTED
+    assert L.lib.hr_solve_ckpt(0x2000, 0x3000, 1, C.byref(p), 5, 0x4000, 0x5000, None, None) == L.HR_ERR_UNSUPPORTED
 
 
 def test_enhance_batch_noalloc_validation(L):
