@@ -1194,7 +1194,7 @@ struct SolveCore {
   int32_t PA[BINS + 1], PB[BINS + 1];               // occupied levels below a / b
   int32_t lane_cells[NT];                           // list build: cells of each lane's rows, then their rank
   int16_t chunk_cls[RMAX * NT];                     // class of chunk u (-1: padding)
-  float redf[6][NT / 64];  // wave partials: sum L^2, sum R'^2, sum R', sum L', change of L, change of R
+  float redf[5][NT / 64];  // wave partials: sum L^2, sum R'', sum L', change of L, change of R
   uint64_t redu[NT / 64];
   double redd[NT / 64];
   int32_t redi[NT / 64];
@@ -1776,6 +1776,12 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   __syncthreads();
 }
 
+// Reciprocal for the per-pass scalars of the solver (the rescalings of Eqs.
+// (14)-(15), the denominators of Eqs. (12)-(13), rho = s / d): the hardware
+// v_rcp_f32, within one ulp, one instruction instead of the ten of an IEEE
+// division that every wave would otherwise repeat in every pass.
+__device__ inline float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Dense (L, R) of a checkpoint into state[0..2 BINS): L' / sum L' and
 // R' / sum R' (Eqs. 14, 15), the values the next pass works with (invL, invR:
 // the reciprocal sums); level k of L at [k], of R at [BINS + k], 0 at
@@ -1838,8 +1844,8 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
   for (int i = t; i <= nA; i += NT) sm.lraw[i] = i < nA ? sm.lc[i] : 0.f;
   for (int j = t; j <= nB; j += NT) sm.rn[j] = j < nB ? sm.rc[j] : 0.f;
   for (int w = t; w < NT / 64; w += NT) {
+    sm.redf[1][w] = w == 0 ? 1.f : 0.f;
     sm.redf[2][w] = w == 0 ? 1.f : 0.f;
-    sm.redf[3][w] = w == 0 ? 1.f : 0.f;
   }
   if (t == 0) {
     sm.lc[nA] = 0.f;
@@ -1873,8 +1879,8 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
   int passes = p.iters;
   for (int it = 0; it < p.iters; ++it) {
     // sums of the previous pass's L', R' (Eqs. 14, 15)
-    const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
-    const float sumL = sums.x, sumR = sums.y, invL = 1.f / sumL, invR = 1.f / sumR;
+    const float2 sums = block_read2<NT>(sm.redf[2], sm.redf[1]);
+    const float sumL = sums.x, sumR = sums.y, invL = rcp_approx(sumL), invR = rcp_approx(sumR);
     if (ckpt && p.ckpt_every > 0 && it % p.ckpt_every == 0)
       write_state<BINS, NT>(sm, ckpt + (size_t)(it / p.ckpt_every) * 2 * BINS, invL, invR);
     // Eqs. (6), (8), (11): class totals d_m and rho_m = s_m / d_m, from the
@@ -1936,7 +1942,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
             y = dpp_get<dpp::BCAST31, 0xc>(acc);  // rows 2, 3 from lane 31
             if (31 >= seg0) acc += y;
           }
-          if (donecls[r] >= 0) sm.rho[donecls[r]] = acc > 0.f ? sm.sd[donecls[r]] * sLR / acc : 0.f;
+          if (donecls[r] >= 0) sm.rho[donecls[r]] = acc > 0.f ? sm.sd[donecls[r]] * sLR * rcp_approx(acc) : 0.f;
         }
       } else {
         // rows of A, each contributing a run of B, summed as a difference of
@@ -2057,7 +2063,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
             for (int w = 0; w < CK; ++w) {
               const int m = CK * cl.q + w;
               if (m >= BINS || sm.PA[m + 1] == sm.PA[m]) continue;  // only the classes of A
-              sm.rho[m] = d[w] > 0.0 ? (float)((double)sm.sd[m] * (double)sLR / d[w]) : 0.f;
+              sm.rho[m] = d[w] > 0.0 ? sm.sd[m] * sLR * rcp_approx((float)d[w]) : 0.f;
             }
           }
         }
@@ -2079,32 +2085,33 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
       }
       wave_partial<NT>(ql, sm.redf[0]);
       if (track) {
-        wave_partial<NT>(dl, sm.redf[4]);
-        wave_partial<NT>(dr, sm.redf[5]);
+        wave_partial<NT>(dl, sm.redf[3]);
+        wave_partial<NT>(dr, sm.redf[4]);
       }
     }
     __syncthreads();
     if (track && it > 0) {
       // stopping rule for the pass just completed (uniform over the block)
-      const float2 ch = block_read2<NT>(sm.redf[4], sm.redf[5]);
+      const float2 ch = block_read2<NT>(sm.redf[3], sm.redf[4]);
       if (ch.x <= p.eps && ch.y <= p.eps) {
         passes = it;
         break;
       }
     }
-    // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta)
+    // Eq. (13): R'_b = (R_b sum_a L_a^2 rho_index(a,b) + beta G_b) / (sum L^2 + beta).
+    // The sweeps keep R'' = (sum L^2 + beta) R' instead: the rescaling of
+    // Eq. (15) removes the common factor, and Eq. (12) below takes it into
+    // its prior term.
     {
-      const float invD = 1.f / (block_read<NT>(sm.redf[0]) + p.beta);
-      float qr = 0.f, sr = 0.f;
+      float sr = 0.f;
       if constexpr (!LIST) {
         sweep_part<NT>(nB, nA, sm.l2c, sm.af, sm.bq, sm.rho, sweep_buf);
         __syncthreads();
         for (int o = t; o < nB; o += NT) {
           const float r = sm.rc[o];
-          const float rn = fmaf(r, sweep_total<NT>(o, nB, nA, sweep_buf), p.beta * sm.gc[o]) * invD;
+          const float rn = fmaf(r, sweep_total<NT>(o, nB, nA, sweep_buf), p.beta * sm.gc[o]);
           sm.rn[o] = rn;
           sm.wc[o] = rn * r;
-          qr += rn * rn;
           sr += rn;
         }
       } else {
@@ -2123,27 +2130,28 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
           }
           acc = group_sum_last(acc, Gc);
           if (k == Gc - 1 && q / Gc < nB) {
-            const float rn = fmaf(r, acc, bg) * invD;
+            const float rn = fmaf(r, acc, bg);
             sm.rn[o] = rn;
             sm.wc[o] = rn * r;
-            qr += rn * rn;
             sr += rn;
           }
         }
       }
-      wave_partial<NT>(qr, sm.redf[1]);
-      wave_partial<NT>(sr, sm.redf[2]);
+      wave_partial<NT>(sr, sm.redf[1]);
     }
     __syncthreads();
-    // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha)
+    // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha).
+    // With R' = R'' / Dr (Dr = sum L^2 + beta), L' is proportional to
+    // L_a sum_b R''_b R_b rho + alpha Dr S_a with a factor common to every
+    // level, which the rescaling of Eq. (14) removes: that is what is kept.
     {
-      const float invD = 1.f / (block_read<NT>(sm.redf[1]) + p.alpha);
+      const float aD = p.alpha * (block_read<NT>(sm.redf[0]) + p.beta);
       float sl = 0.f;
       if constexpr (!LIST) {
         sweep_part<NT>(nA, nB, sm.wc, sm.bq, sm.af, sm.rho, sweep_buf);
         __syncthreads();
         for (int o = t; o < nA; o += NT) {
-          const float ln = fmaf(sm.lc[o], sweep_total<NT>(o, nA, nB, sweep_buf), p.alpha * sm.sc[o]) * invD;
+          const float ln = fmaf(sm.lc[o], sweep_total<NT>(o, nA, nB, sweep_buf), aD * sm.sc[o]);
           sm.lraw[o] = ln;
           sl += ln;
         }
@@ -2153,7 +2161,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
           const int q = base + t;
           const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
           const int s0 = k * Lr;
-          const float lo = sm.lc[o], as = p.alpha * sm.sc[o];
+          const float lo = sm.lc[o], as = aD * sm.sc[o];
           float acc = 0.f;
           if constexpr (TAB) {
             const uint32_t* trow = reinterpret_cast<const uint32_t*>(tab + o * nBp);
@@ -2163,19 +2171,19 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
           }
           acc = group_sum_last(acc, Gr);
           if (k == Gr - 1 && q / Gr < nA) {
-            const float ln = fmaf(lo, acc, as) * invD;
+            const float ln = fmaf(lo, acc, as);
             sm.lraw[o] = ln;
             sl += ln;
           }
         }
       }
-      wave_partial<NT>(sl, sm.redf[3]);
+      wave_partial<NT>(sl, sm.redf[2]);
     }
     __syncthreads();
   }
   // Eqs. (15), (14) of the last pass
   {
-    const float2 sums = block_read2<NT>(sm.redf[3], sm.redf[2]);
+    const float2 sums = block_read2<NT>(sm.redf[2], sm.redf[1]);
     const float invL = 1.f / sums.x, invR = 1.f / sums.y;
     if (ckpt && p.ckpt_every > 0 && p.iters % p.ckpt_every == 0)
       write_state<BINS, NT>(sm, ckpt + (size_t)(p.iters / p.ckpt_every) * 2 * BINS, invL, invR);

@@ -86,3 +86,17 @@ def oracle_hists(img: np.ndarray, bins: int):
     hS = O.count_histogram(V, bins)
     graw, gmax, hG = O.gradient_histogram(V, bins)
     return hS, graw, gmax, hG
+
+
+def gpu_params(H, p: "O.Params"):
+    """The library's Params for the oracle's: the same numbers, the readings
+    as HR_VARIANT_* bits."""
+    from paper_2510_21100_amd import _lib as L
+
+    variant = 0
+    variant |= {"fwd_l1": 0, "fwd_l2": L.HR_VARIANT_GRAD_L2, "sobel_l1": L.HR_VARIANT_GRAD_SOBEL}[p.grad_op]
+    variant |= L.HR_VARIANT_GRAD_CLIP if p.grad_rescale == "clip" else 0
+    variant |= L.HR_VARIANT_UPDATE_DIV if p.update == "div" else 0
+    variant |= L.HR_VARIANT_INIT_UNIFORM if p.init_l == "uniform" else 0
+    return H.Params(bins=p.bins, iters=p.iters, alpha=p.alpha, beta=p.beta, gamma=p.gamma, eps=p.eps,
+                    variant=variant)

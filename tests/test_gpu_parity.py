@@ -6,8 +6,8 @@ import torch
 
 import oracle as O
 from synthetic import edge_images
-from gpu_cases import (REL_TOL, cfg_image, lut_contract, oracle_hists, padded_gpu, pixel_contract,
-                       rel_err, to_gpu, to_np)
+from gpu_cases import (REL_TOL, cfg_image, gpu_params, lut_contract, oracle_hists, padded_gpu,
+                       pixel_contract, rel_err, to_gpu, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +92,7 @@ def _solve_case(H, img, params):
     N = int(hS.sum())
     hv = torch.from_numpy(hS.astype(np.int32)).cuda()
     hg = torch.from_numpy(hG.astype(np.int32)).cuda()
-    illum, refl, target = H.solve(hv, hg, N, H.Params(**params.__dict__))
+    illum, refl, target = H.solve(hv, hg, N, gpu_params(H, params))
     torch.cuda.synchronize()
     lv, rv, _ = O.solve(hS, hG, params)
     tref = O.target_histogram(lv, rv, N, params.gamma)
@@ -198,7 +198,7 @@ def test_match_in_place_and_strided_output(H):
 def test_end_to_end_plain(H, cfg, shape, bits):
     img = cfg_image(cfg, *shape, bits=bits)
     params = O.Params(bins=1 << bits, iters=50)
-    out, ex = H.enhance(to_gpu(img), H.Params(**params.__dict__))
+    out, ex = H.enhance(to_gpu(img), gpu_params(H, params))
     torch.cuda.synchronize()
     ref = O.enhance(img, params)
     assert np.array_equal(to_np(ex["hist_v"]).astype(np.int64), ref["hS"])

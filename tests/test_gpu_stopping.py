@@ -8,7 +8,7 @@ import torch
 
 import oracle as O
 from synthetic import config_seed, edge_images, make_batch_shapes, make_image
-from gpu_cases import REL_TOL, lut_contract, oracle_hists, padded_gpu, rel_err, to_gpu, to_np
+from gpu_cases import REL_TOL, gpu_params, lut_contract, oracle_hists, padded_gpu, rel_err, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,7 @@ def _solve_gpu(H, hS, hG, params):
     hv = torch.from_numpy(hS.astype(np.int32)).cuda()
     hg = torch.from_numpy(hG.astype(np.int32)).cuda()
     passes = torch.full((1,), -1, dtype=torch.int32, device="cuda")
-    illum, refl, target = H.solve(hv, hg, int(hS.sum()), H.Params(**params.__dict__), passes=passes)
+    illum, refl, target = H.solve(hv, hg, int(hS.sum()), gpu_params(H, params), passes=passes)
     torch.cuda.synchronize()
     return to_np(illum), to_np(refl), to_np(target), int(passes.item())
 
