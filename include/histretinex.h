@@ -121,7 +121,9 @@ typedef struct {
  * one pass of the persistent workgroup over its pixels: 1024 threads x 8 px
  * (8-bit) or x 4 px (10-bit).
  *  tile_steps  : steps per histogram work item
- *  wg_per_cu   : persistent workgroups per compute unit (1..8)
+ *  wg_per_cu   : persistent workgroups per compute unit (1..8; at launch
+ *                capped at what one CU holds at once -- one, with the batched
+ *                kernel's LDS and registers on gfx950)
  *  remap_steps : steps per remap work item
  *  Zero in a field selects the built-in default. */
 typedef struct {

@@ -77,6 +77,7 @@ struct hr_workspace {
   int max_images = 0;
   int max_bins = 0;
   int cu_count = 0;
+  int max_wg[2] = {1, 1};  // batched workgroups one CU holds, 8-bit / 10-bit kernel
   hr_schedule sched{kDefaultTileSteps, kDefaultWgPerCu, kDefaultRemapSteps};
   uint32_t* d_flags = nullptr;   // [0] sticky flags, [1] plain-hist ticket
   uint32_t* d_graw = nullptr;    // plain: raw gradient histogram scratch [2*max_bins]
@@ -249,6 +250,7 @@ hr_status hr_workspace_create(int32_t max_images, int32_t max_bins, hr_workspace
   } while (0)
   HR_HIP_WS(hipGetDevice(&ws->device));
   HR_HIP_WS(hipDeviceGetAttribute(&ws->cu_count, hipDeviceAttributeMultiprocessorCount, ws->device));
+  for (int b = 0; b < 2; ++b) ws->max_wg[b] = std::max(1, hr::launch::batch_max_wg_per_cu(b == 0 ? 8 : 10));
   HR_HIP_WS(hipMalloc(&ws->d_flags, 64));
   HR_HIP_WS(hipMalloc(&ws->d_graw, sizeof(uint32_t) * 2 * max_bins));
   HR_HIP_WS(hipMalloc(&ws->d_lut, sizeof(uint16_t) * max_bins));
@@ -484,7 +486,9 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
   hdr.out = hr::BatchOut{luts, illum, refl, target, passes};
   std::memcpy(stage, &hdr, sizeof(hdr));
 
-  const int grid = std::max(1, ws->cu_count * ws->sched.wg_per_cu);
+  // more persistent workgroups than the CUs can hold at once would only queue
+  // behind the resident ones
+  const int grid = std::max(1, ws->cu_count * std::min(ws->sched.wg_per_cu, ws->max_wg[bits == 8 ? 0 : 1]));
   GraphEntry& g = ws->graphs[slot][bits == 8 ? 0 : 1];
   if (!g.valid || g.grid != grid) {
     if (g.exec) {

@@ -1824,8 +1824,12 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
   const int nAp = sm.nAp, nBp = sm.nBp;
   // dense sweeps with a class list: output o split over G lanes (a power of
   // two); slice k covers L inputs (a multiple of 4), zero-padded past the end
-  const int Gc = nB <= NT ? pow2_floor64(NT / nB) : 1;
-  const int Gr = nA <= NT ? pow2_floor64(NT / nA) : 1;
+  // lanes the two dense sweeps spread their outputs over; waves past them
+  // skip the sweep and contribute zero partial sums
+  constexpr int SWEEP_LANES = NT;
+  const int Gc = nB <= SWEEP_LANES ? pow2_floor64(SWEEP_LANES / nB) : 1;
+  const int Gr = nA <= SWEEP_LANES ? pow2_floor64(SWEEP_LANES / nA) : 1;
+  const bool col_wave = (t & ~63) < nB * Gc, row_wave = (t & ~63) < nA * Gr;
   const int Lc = ((nA + Gc - 1) / Gc + 3) & ~3, Lr = ((nB + Gr - 1) / Gr + 3) & ~3;
   // without a class list the slice sums of sweep_part go to spare (4 NT floats)
   float* sweep_buf = reinterpret_cast<float*>(sm.spare);
@@ -2137,7 +2141,10 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
           }
         }
       }
-      wave_partial<NT>(sr, sm.redf[1]);
+      if (!LIST || col_wave)
+        wave_partial<NT>(sr, sm.redf[1]);
+      else if (lane == 63)
+        sm.redf[1][t >> 6] = 0.f;
     }
     __syncthreads();
     // Eq. (12): L'_a = (L_a sum_b R'_b R_b rho_index(a,b) + alpha S_a) / (sum R'^2 + alpha).
@@ -2177,7 +2184,10 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
           }
         }
       }
-      wave_partial<NT>(sl, sm.redf[2]);
+      if (!LIST || row_wave)
+        wave_partial<NT>(sl, sm.redf[2]);
+      else if (lane == 63)
+        sm.redf[2][t >> 6] = 0.f;
     }
     __syncthreads();
   }

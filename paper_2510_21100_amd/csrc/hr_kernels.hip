@@ -509,6 +509,13 @@ hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgC
   return hipGetLastError();
 }
 
+int batch_max_wg_per_cu(int bits) {
+  int n = 0;
+  const hipError_t e = bits == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<8>, NT_BATCH, 0)
+                                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<10>, NT_BATCH, 0);
+  return e == hipSuccess ? n : 0;
+}
+
 int step_px(int bits) { return bits == 8 ? Pix<8, NT_PIX>::STEP : Pix<10, NT_PIX>::STEP; }
 int batch_step_px(int bits) { return bits == 8 ? Pix<8, NT_BATCH>::STEP : Pix<10, NT_BATCH>::STEP; }
 int max_width(int bits) { return bits == 8 ? MaxWidth<8>::value : MaxWidth<10>::value; }

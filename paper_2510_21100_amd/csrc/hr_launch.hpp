@@ -124,6 +124,9 @@ hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut,
 hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lut, hipStream_t s);
 hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
                  uint32_t* lists, int64_t lists_stride, uint32_t* flags, hipStream_t s);
+// persistent workgroups of the batched kernel one CU can hold (its LDS and
+// registers allow), 0 on a query failure
+int batch_max_wg_per_cu(int bits);
 int step_px(int bits);
 int batch_step_px(int bits);
 int max_width(int bits);

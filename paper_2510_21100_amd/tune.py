@@ -18,6 +18,8 @@ import os
 from typing import Sequence
 
 TILE_STEPS = (8, 16, 24, 32, 48, 64, 128)
+# one batched workgroup per CU: its LDS (about 150 KB) and registers leave room
+# for no second one, and the library caps the grid at what the CUs hold
 WG_PER_CU = (1,)
 REMAP_STEPS = (4, 8, 16, 24, 32, 48, 64)
 
