@@ -1607,6 +1607,12 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   sm.lane_cells[t] = mine;
   for (int u = t; u < RMAX * NT; u += NT) sm.chunk_cls[u] = -1;
   for (int m = t; m < BINS; m += NT) sm.csz[m] = 0;
+  // the levels as the class tables take them: a, and b / (l-1) in FP32
+  // (zero padded)
+  for (int q = t; q < BINS + SolveCore<BINS, NT>::PAD; q += NT) {
+    sm.af[q] = q < nA ? (float)sm.A[q] : 0.f;
+    sm.bq[q] = q < nB ? (float)sm.B[q] / (float)(BINS - 1) : 0.f;
+  }
   __syncthreads();
   int before = 0;
   if (cl.q >= 0) {
@@ -1621,8 +1627,20 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
     mx = max(mx, c);
     tot += c;
   }
-  mx = block_max<NT>(mx, sm.redi);
-  const int nc = block_sum<NT>(tot, sm.redi);
+  // largest class and total cells in one block reduction
+  mx = wave_max(mx);
+  tot = wave_sum(tot);
+  if ((t & 63) == 0) {
+    sm.redi[t >> 6] = mx;
+    sm.redu[t >> 6] = (uint64_t)tot;
+  }
+  __syncthreads();
+  int nc = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    mx = max(mx, sm.redi[i]);
+    nc += (int)sm.redu[i];
+  }
   if (t < 64) {
     // one wave lays the chunks out, classes in order, each class's chunks
     // inside one 64-chunk group: a class that would straddle a group
@@ -1751,26 +1769,32 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   }
   if (sm.tab_lds) {
     // four classes per word; rows padded to nBp (nAp) bytes with class 0
+    // (the zero padding of af and bq gives class 0).  A row has at most 64
+    // words (nB, nA <= 256), so a wave covers 64 / words whole rows at a
+    // time and each lane keeps one word position: no index division in the
+    // loops, one FMA per class (class_of on a and b / (l-1), exact).
     uint32_t* tab = reinterpret_cast<uint32_t*>(class_table(sm));
     uint32_t* tabT = tab + (nA * sm.nBp >> 2);
-    const int wr = sm.nBp >> 2, wc = sm.nAp >> 2;
-    for (int q = t; q < nA * wr; q += NT) {
-      const int i = q / wr, j0 = (q - i * wr) * 4;
-      const int a = sm.A[i];
-      uint32_t w = 0;
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-        if (j0 + x < nB) w |= (uint32_t)class_of<BINS>(a, sm.B[j0 + x]) << (8 * x);
-      tab[q] = w;
+    const int wave = t >> 6, lane = t & 63;
+    {
+      const int wr = sm.nBp >> 2, rpw = 64 / wr, sub = lane / wr, w = lane - sub * wr;
+      if (sub < rpw) {
+        const float4 v = *reinterpret_cast<const float4*>(&sm.bq[4 * w]);
+        for (int i = wave * rpw + sub; i < nA; i += (NT / 64) * rpw) {
+          const float a = sm.af[i];
+          tab[i * wr + w] = class_of(a, v.x) | class_of(a, v.y) << 8 | class_of(a, v.z) << 16 | class_of(a, v.w) << 24;
+        }
+      }
     }
-    for (int q = t; q < nB * wc; q += NT) {
-      const int j = q / wc, k0 = (q - j * wc) * 4;
-      const int b = sm.B[j];
-      uint32_t w = 0;
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-        if (k0 + x < nA) w |= (uint32_t)class_of<BINS>(sm.A[k0 + x], b) << (8 * x);
-      tabT[q] = w;
+    {
+      const int wc = sm.nAp >> 2, rpw = 64 / wc, sub = lane / wc, w = lane - sub * wc;
+      if (sub < rpw) {
+        const float4 u = *reinterpret_cast<const float4*>(&sm.af[4 * w]);
+        for (int j = wave * rpw + sub; j < nB; j += (NT / 64) * rpw) {
+          const float v = sm.bq[j];
+          tabT[j * wc + w] = class_of(u.x, v) | class_of(u.y, v) << 8 | class_of(u.z, v) << 16 | class_of(u.w, v) << 24;
+        }
+      }
     }
   }
   __syncthreads();
