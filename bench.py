@@ -322,6 +322,37 @@ def time_batched(H, gimgs, outs, params, ws, steps: int, warmup: int, device_war
     return wall * 1e3 / steps, launch_ms, n_w
 
 
+def time_in_flight(H, gimgs, params, sched, bins, streams: int, steps: int):
+    """Consecutive batches on `streams` streams, each with its own workspace
+    and outputs (batch k on stream k mod streams): the tail of one launch
+    (the last solves, while most CUs are idle) overlaps the next launch's
+    histogram pass.  Returns (wall ms per batch, outputs of every stream equal)."""
+    import torch
+
+    wss = [H.Workspace(max_images=len(gimgs), max_bins=bins) for _ in range(streams)]
+    for w in wss:
+        w.set_schedule(*sched)
+    outs = [[torch.empty_like(g) for g in gimgs] for _ in range(streams)]
+    strs = [torch.cuda.Stream() for _ in range(streams)]
+    torch.cuda.synchronize()
+    for k in range(2 * streams):
+        with torch.cuda.stream(strs[k % streams]):
+            H.enhance_batch(gimgs, params, outs=outs[k % streams], ws=wss[k % streams])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        with torch.cuda.stream(strs[k % streams]):
+            H.enhance_batch(gimgs, params, outs=outs[k % streams], ws=wss[k % streams])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    equal = all(torch.equal(a, b) for o in outs[1:] for a, b in zip(outs[0], o))
+    for w in wss:
+        w.close()
+    del outs
+    torch.cuda.empty_cache()
+    return ms, equal
+
+
 def batched_line(H, tune, name, imgs, bits, args, dev, with_plain: bool):
     """The batched form on one workload: Mpix/s, roofline of the persistent
     kernel, schedule; with_plain adds the one-image form and the solver alone."""
@@ -364,6 +395,12 @@ def batched_line(H, tune, name, imgs, bits, args, dev, with_plain: bool):
         },
         "device_warmup_calls": n_w,
     }
+    if args.in_flight > 1:
+        fl_ms, fl_equal = time_in_flight(H, gimgs, params, sched, bins, args.in_flight, args.steps)
+        res["in_flight"] = {"streams": args.in_flight, "ms_per_batch": round(fl_ms, 4),
+                            "value": round(npix / (fl_ms * 1e-3) / 1e6, 1), "unit": "Mpix/s",
+                            "over_one_stream": round(ms_step / fl_ms, 3), "outputs_equal": fl_equal,
+                            "form": "consecutive batches on separate streams, workspaces and outputs"}
     if args.calibrate_copy_mb > 0 and name == args.workload:
         nbytes = args.calibrate_copy_mb << 20
         src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
@@ -538,6 +575,8 @@ def main():
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--remap-steps", type=int, default=0)
     ap.add_argument("--schedule", default=os.path.join(ROOT, "paper_2510_21100_amd", "schedule.json"))
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="also time consecutive batches on this many streams (0 or 1: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-image form and the solver timing")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiated-form timing")
     ap.add_argument("--no-extra", action="store_true",
@@ -594,6 +633,8 @@ def main():
         "plain": head.get("plain"),
         "solve_us_per_image": head.get("solve_us_per_image"),
     }
+    if "in_flight" in head:
+        line["in_flight"] = head["in_flight"]
     if extra and args.workload != "uhd16":
         d10, b10, j10 = workload("uhd16")
         u = batched_line(H, tune, "uhd16", generate(j10, args.workers), b10, args, dev, with_plain=not args.no_plain)

@@ -695,9 +695,12 @@ struct HistTileSplit {
   uint32_t clamped = 0;
   static constexpr uint32_t GSMALL = SM::GSMALL;
 
+  // `producer` is read from lane 0 as a scalar: NH is a multiple of 64, so the
+  // halves are whole waves, and a scalar branch keeps the two loops (and
+  // their registers) apart
   __device__ HistTileSplit(const ImgDesc& d_, int64_t p0, int64_t p1, SM& sm_)
       : d(d_), sm(sm_), P0(p0), P1(p1), N(d_.npix), E(min(p1 + (int64_t)d_.W, d_.npix)), W(d_.W),
-        tt(threadIdx.x & (NH - 1)), step_mod_w(STEP % d_.W), producer(threadIdx.x < NH),
+        tt(threadIdx.x & (NH - 1)), step_mod_w(STEP % d_.W), producer(__builtin_amdgcn_readfirstlane((int)threadIdx.x) < NH),
         hs(sm_.hs + (threadIdx.x & (SM::REPS - 1))), hg(sm_.hg + (threadIdx.x & (REP - 1))),
         hgl(sm_.hgs + (threadIdx.x & 63)) {
     x = (int)((P0 + (int64_t)tt * PX) % W);
@@ -1853,7 +1856,10 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
   constexpr int SWEEP_LANES = NT;
   const int Gc = nB <= SWEEP_LANES ? pow2_floor64(SWEEP_LANES / nB) : 1;
   const int Gr = nA <= SWEEP_LANES ? pow2_floor64(SWEEP_LANES / nA) : 1;
-  const bool col_wave = (t & ~63) < nB * Gc, row_wave = (t & ~63) < nA * Gr;
+  // the first thread of this wave, as a scalar: the wave-level tests below
+  // compile to scalar branches
+  const int wave0 = __builtin_amdgcn_readfirstlane(t & ~63);
+  const bool col_wave = wave0 < nB * Gc, row_wave = wave0 < nA * Gr;
   const int Lc = ((nA + Gc - 1) / Gc + 3) & ~3, Lr = ((nB + Gr - 1) / Gr + 3) & ~3;
   // without a class list the slice sums of sweep_part go to spare (4 NT floats)
   float* sweep_buf = reinterpret_cast<float*>(sm.spare);
@@ -1919,7 +1925,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
         // one chunk per lane and round; a class is summed inside its wave
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-          if (r >= R || r * NT + (t & ~63) >= nchunks) break;  // whole wave of padding
+          if (r >= R || r * NT + wave0 >= nchunks) break;  // whole wave of padding
           const int u = r * NT + t;
           const cell_t* cp = cells + (size_t)u * CS;
           // four partial sums (cell position mod 4), fixed order; eight cells
@@ -2144,7 +2150,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
         }
       } else {
         for (int base = 0; base < nB * Gc; base += NT) {
-          if (base + (t & ~63) >= nB * Gc) break;  // whole wave past the outputs
+          if (base + wave0 >= nB * Gc) break;  // whole wave past the outputs
           const int q = base + t;
           const int o = min(q / Gc, nB - 1), k = q & (Gc - 1);
           const int s0 = k * Lc;  // a multiple of 4
@@ -2188,7 +2194,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
         }
       } else {
         for (int base = 0; base < nA * Gr; base += NT) {
-          if (base + (t & ~63) >= nA * Gr) break;  // whole wave past the outputs
+          if (base + wave0 >= nA * Gr) break;  // whole wave past the outputs
           const int q = base + t;
           const int o = min(q / Gr, nA - 1), k = q & (Gr - 1);
           const int s0 = k * Lr;
