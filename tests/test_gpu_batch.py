@@ -106,6 +106,35 @@ def test_batch_schedules_agree(H):
     ws.close()
 
 
+def test_batches_in_flight_on_streams(H):
+    """Consecutive batches on three streams, each with its own workspace and
+    outputs (launches overlap on the device): every batch equals the batch
+    run alone, for both bit depths."""
+    for bits, shapes in ((8, SHAPES[:5]), (10, [(216, 384), (61, 700), (400, 33)])):
+        imgs = _batch_imgs(shapes, bits=bits, cfg=3 if bits == 8 else 4)
+        gimgs = [to_gpu(x) for x in imgs]
+        params = H.Params(bins=1 << bits)
+        ref, _ = H.enhance_batch(gimgs, params)
+        torch.cuda.synchronize()
+        wss = [H.Workspace(max_images=len(gimgs), max_bins=1 << bits) for _ in range(3)]
+        streams = [torch.cuda.Stream() for _ in range(3)]
+        outs = [[torch.empty_like(g) for g in gimgs] for _ in range(3)]
+        for rnd in range(3):
+            for k in range(3):
+                for o in outs[k]:
+                    o.zero_()
+            torch.cuda.synchronize()
+            for k in range(3):
+                with torch.cuda.stream(streams[k]):
+                    H.enhance_batch(gimgs, params, outs=outs[k], ws=wss[k])
+            torch.cuda.synchronize()
+            for k in range(3):
+                for i, (a, b) in enumerate(zip(outs[k], ref)):
+                    assert torch.equal(a, b), (bits, rnd, k, i)
+        for w in wss:
+            w.close()
+
+
 def test_batch_vs_oracle(H):
     imgs = _batch_imgs([(300, 400), (128, 999)])
     outs, ex = H.enhance_batch([to_gpu(x) for x in imgs], H.Params(bins=256), extras=True)
