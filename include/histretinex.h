@@ -250,9 +250,9 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Takes no workspace and allocates nothing (no hipMalloc, no
  * hipFree, no allocating library routine): the descriptor table travels as
- * a kernel argument, and the queue, counters, per-image states and solver
- * scratch live in one fixed device array of the library, about 3.6 MB on
- * each GPU it runs on, held until the process ends.  Every call on a GPU
+ * a kernel argument, and the queue, counters and per-image states live in
+ * one fixed device array of the library, about 0.5 MB on each GPU it runs
+ * on, held until the process ends.  Every call on a GPU
  * shares that array: two calls that overlap on one GPU (different streams,
  * or threads without ordering) race; calls ordered on one stream do not.
  * Each call clears what must start at zero.  Results are those of

@@ -82,8 +82,6 @@ struct hr_workspace {
   uint32_t* d_flags = nullptr;   // [0] sticky flags, [1] plain-hist ticket
   uint32_t* d_graw = nullptr;    // plain: raw gradient histogram scratch [2*max_bins]
   uint16_t* d_lut = nullptr;     // plain: LUT scratch [max_bins]
-  uint32_t* d_lists = nullptr;   // per image: 3 * bins^2 words of solver lists
-  int64_t lists_words = 0;       // words per image slot
   uint8_t* d_table = nullptr;    // BatchHeader + ImgDesc[max_images] + ImgCounters[max_images]
   uint32_t* d_state = nullptr;   // ImageState per image
   // d_state's partial slots are zero in the layout of this bit depth (0: all
@@ -205,7 +203,6 @@ void release(hr_workspace* ws) {
   (void)hipFree(ws->d_flags);
   (void)hipFree(ws->d_graw);
   (void)hipFree(ws->d_lut);
-  (void)hipFree(ws->d_lists);
   (void)hipFree(ws->d_table);
   (void)hipFree(ws->d_state);
   (void)hipFree(ws->d_diff);
@@ -254,8 +251,6 @@ hr_status hr_workspace_create(int32_t max_images, int32_t max_bins, hr_workspace
   HR_HIP_WS(hipMalloc(&ws->d_flags, 64));
   HR_HIP_WS(hipMalloc(&ws->d_graw, sizeof(uint32_t) * 2 * max_bins));
   HR_HIP_WS(hipMalloc(&ws->d_lut, sizeof(uint16_t) * max_bins));
-  ws->lists_words = 3LL * max_bins * max_bins;
-  HR_HIP_WS(hipMalloc(&ws->d_lists, sizeof(uint32_t) * ws->lists_words * max_images));
   HR_HIP_WS(hipMalloc(&ws->d_table, table_bytes(max_images)));
   HR_HIP_WS(hipMalloc(&ws->d_state, sizeof(uint32_t) * hr::ImageState::words(max_bins) * max_images));
   HR_HIP_WS(hipMalloc(&ws->d_diff, diff_bytes(max_images)));
@@ -395,7 +390,7 @@ hr_status hr_solve(const uint32_t* hist_v, const uint32_t* hist_grad, int64_t np
                                      static_cast<hipStream_t>(stream)));
     return HR_OK;
   }
-  HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, ws->d_lists, illum, refl, target, passes,
+  HR_HIP(hr::launch::solve(p->bins, hist_v, hist_grad, npix, sp, illum, refl, target, passes,
                            ws->d_flags, static_cast<hipStream_t>(stream)));
   return HR_OK;
 }
@@ -503,8 +498,8 @@ hr_status hr_enhance_batch(const hr_image* in, void* const* out, const int64_t* 
     hipGraph_t graph = nullptr;
     HR_HIP(hipStreamBeginCapture(ws->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = hipMemcpyAsync(ws->d_table, stage, table_bytes(ws->max_images), hipMemcpyHostToDevice, ws->capture);
-    hipError_t e3 = e1 == hipSuccess ? hr::launch::batch(bits, grid, hdr_d, desc_d, ctr_d, st_d, ws->d_lists,
-                                                        3LL * bins * bins, ws->d_flags, ws->capture)
+    hipError_t e3 = e1 == hipSuccess ? hr::launch::batch(bits, grid, hdr_d, desc_d, ctr_d, st_d, ws->d_flags,
+                                                        ws->capture)
                                      : e1;
     hipError_t e4 = hipStreamEndCapture(ws->capture, &graph);
     if (e3 != hipSuccess) {
@@ -602,8 +597,8 @@ hr_status hr_solve_ckpt(const uint32_t* hist_v, const uint32_t* hist_grad, int32
   if (n > ws->max_images) return fail(HR_ERR_WORKSPACE, "hr_solve_ckpt: n exceeds the workspace's max_images");
   hr::SolveParams sp = solve_params(p);
   sp.ckpt_every = ckpt_every;
-  HR_HIP(hr::launch::solve_ckpt(n, hist_v, hist_grad, sp, p->iters / ckpt_every + 1, ckpt, target, ws->d_lists,
-                                ws->d_flags, static_cast<hipStream_t>(stream)));
+  HR_HIP(hr::launch::solve_ckpt(n, hist_v, hist_grad, sp, p->iters / ckpt_every + 1, ckpt, target, ws->d_flags,
+                                static_cast<hipStream_t>(stream)));
   return HR_OK;
 }
 

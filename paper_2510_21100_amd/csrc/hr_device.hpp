@@ -60,7 +60,15 @@ __device__ inline uint32_t umax3(uint32_t a, uint32_t b, uint32_t c) {
 // single thread fences and signals; on the receiving side a single thread
 // observes the signal and fences before the barrier that releases the rest.
 __device__ inline void drain_memory() { __builtin_amdgcn_s_waitcnt(0); }
-__device__ inline void fence_release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+// Release at agent scope before a signal: the fence writes this XCD's L2 back
+// to memory, and the wait makes that write-back complete before the signal's
+// store or atomic is issued (the compiler does not always place a wait between
+// the write-back and a later store, and a reader on another XCD could then see
+// the signal before the data).
+__device__ inline void fence_release_agent() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
+}
 __device__ inline void fence_acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Workgroup barrier for the pixel loops.  __syncthreads() waits for every
@@ -826,7 +834,7 @@ struct HistTileSplit {
           const uint32_t ve = lane_dyn<pix_t>(own, e);
           const uint32_t vre = (e + 1 < PX) ? lane_dyn<pix_t>(own, e + 1) : right_last;
           const uint32_t vde = lane_dyn<pix_t>(dn, e);
-          atomicSub(gslot(grad_l1(vre, ve, vde)), 1u);
+          __hip_atomic_fetch_sub(gslot(grad_l1(vre, ve, vde)), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           atomicAdd(gslot(grad_l1(ve, ve, vde)), 1u);
         }
       } else {
@@ -1202,7 +1210,7 @@ struct SolveCore {
   double redd[NT / 64];
   int32_t redi[NT / 64];
   int32_t nA, nB, nc, C, CS, R, nAp, nBp;           // CS: cell stride of a chunk
-  int32_t cells_lds, tab_lds, use_list;
+  int32_t tab_lds, use_list;
 };
 
 // The class list and the class tables take the LDS left in `budget` bytes.
@@ -1574,6 +1582,14 @@ __device__ inline float sweep_total(int o, int nout, int nin, const float* part)
   return acc;
 }
 
+// Largest nA nB for which the class list is used at 256 levels: measured on
+// one CU, the list form's passes cost about 2 us + 0.25 us per thousand
+// cells (the list gathers two values per cell) and the running-sum form's
+// about 5 us + 0.09 us per thousand; with the list's build included the two
+// totals cross between 36k cells (list 462 us, running sums 482 us) and 44k
+// (655 us against 534 us).
+constexpr int64_t LIST_MAX_CELLS = 40000;
+
 // Class-major list of the cells (i, j) of A x B whose class has s_m > 0
 // (other classes have rho = 0 and their totals are never used), cut into
 // chunks of exactly C cells (C a multiple of 4; the last chunk of a class
@@ -1581,10 +1597,11 @@ __device__ inline float sweep_total(int o, int nout, int nin, const float* part)
 // NT lanes; the chunks of a class are consecutive and never cross a 64-chunk
 // boundary, so a class is summed inside one wave of one round.  Within a
 // class the cells are ordered by row and column.  Chunk u holds its cells
-// contiguously from u * CS.  256 levels only.
+// contiguously from u * CS.  256 levels only.  The list is built, and used,
+// only when the occupied cells nA nB are at most LIST_MAX_CELLS and the list
+// fits in LDS; larger images take the running-sum form of the class totals.
 template <int BINS, int NT, int BUDGET>
-__device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells,
-                                 int64_t gcap) {
+__device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
   constexpr int MAXCH = 32;  // chunks per class
@@ -1592,6 +1609,19 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
   static_assert(BINS <= NT * RMAX / 2, "every class must get a chunk");
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
+  if ((int64_t)nA * nB > LIST_MAX_CELLS) {  // the same in every thread
+    if (t == 0) {
+      sm.use_list = 0;
+      sm.tab_lds = 0;
+      sm.C = 0;
+      sm.CS = 0;
+      sm.R = 0;
+      sm.nAp = (nA + 3) & ~3;
+      sm.nBp = (nB + 3) & ~3;
+    }
+    __syncthreads();
+    return;
+  }
   // The (class, row) pairs over balanced lanes (class q = A[q] has the rows
   // q..nA-1), each lane a contiguous range of its class's rows: the lane's
   // cells, then its rank in the class's row-major order from the lanes before
@@ -1702,18 +1732,17 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
       sm.R = max(1, (pos + NT - 1) / NT);
       const int64_t ncells = (int64_t)sm.R * NT * sm.CS;
       const int64_t cell_bytes = ncells * sizeof(cell_t);
-      sm.cells_lds = cell_bytes <= (int64_t)sizeof(sm.spare) ? 1 : 0;
-      sm.use_list = (sm.cells_lds || ncells <= gcap) ? 1 : 0;
+      sm.use_list = cell_bytes <= (int64_t)sizeof(sm.spare) ? 1 : 0;
       sm.nAp = (nA + 3) & ~3;
       sm.nBp = (nB + 3) & ~3;
       const int64_t tab_bytes = (int64_t)nA * sm.nBp + (int64_t)nB * sm.nAp + 16;
-      sm.tab_lds = (sm.cells_lds && ((cell_bytes + 15) & ~15) + tab_bytes <= (int64_t)sizeof(sm.spare)) ? 1 : 0;
+      sm.tab_lds = (sm.use_list && ((cell_bytes + 15) & ~15) + tab_bytes <= (int64_t)sizeof(sm.spare)) ? 1 : 0;
     }
   }
   __syncthreads();
   if (!sm.use_list) return;  // the solver sums the classes without a list
   const int C = sm.C, CS = sm.CS, R = sm.R;
-  cell_t* cells = sm.cells_lds ? cell_store(sm) : gcells;
+  cell_t* cells = cell_store(sm);
   const cell_t zero_cell = (cell_t)(nA | (nB << SH));  // lc[nA] = rc[nB] = 0
   for (int m = t; m < BINS; m += NT) {
     const int c = sm.csz[m];
@@ -1824,9 +1853,8 @@ __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, 
 // The Alg. 1 loop; returns the number of passes run.  LIST: class totals
 // from the class list and sweeps over power-of-two lane groups per output
 // (else class totals from running sums over row runs, four classes per lane,
-// and sweeps with four outputs per lane over input slices); CELLS_LDS / TAB:
-// where the list and the class tables live, so that every access compiles to
-// its address space.
+// and sweeps with four outputs per lane over input slices); TAB: the class
+// tables are in LDS (else the sweeps compute the classes).
 //
 // Stopping rule (Alg. 1): at most p.iters passes; with p.eps > 0 the loop
 // also ends after a pass whose changes of the normalised L and R both have a
@@ -1834,9 +1862,8 @@ __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, 
 // the next pass's class sweep, which is where the new L and R meet the old
 // ones: the changes of pass t are summed there, in pass t + 1, and the
 // decision (the same bits in every lane) is taken after its barrier.
-template <int BINS, int NT, int BUDGET, bool LIST, bool CELLS_LDS, bool TAB>
-__device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const typename CellT<BINS>::type* __restrict__ gcells,
-                        const SolveParams& p, float* ckpt) {
+template <int BINS, int NT, int BUDGET, bool LIST, bool TAB>
+__device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const SolveParams& p, float* ckpt) {
   using cell_t = typename CellT<BINS>::type;
   constexpr int SH = CellT<BINS>::SHIFT;
   constexpr uint32_t MASK = (1u << SH) - 1;
@@ -1845,7 +1872,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
   static_assert(SolveSmem<BINS, NT, BUDGET>::FREE >= 8 * NT, "lane partials of the class sweep");
   const int t = threadIdx.x, lane = t & 63;
   const int nA = sm.nA, nB = sm.nB, C = sm.C, CS = sm.CS, R = sm.R;
-  const cell_t* cells = CELLS_LDS ? cell_store(sm) : gcells;
+  const cell_t* cells = cell_store(sm);
   const uint8_t* tab = class_table(sm);
   const uint8_t* tabT = tab + nA * sm.nBp;
   const int nAp = sm.nAp, nBp = sm.nBp;
@@ -2238,7 +2265,6 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const ty
 constexpr int SOLVE_BUDGET_PLAIN = 150 * 1024;
 // solver scratch per image in global memory (32-bit words), as allocated by
 // the workspace: 3 * l^2
-template <int BINS> constexpr int64_t LIST_WORDS = 3LL * BINS * BINS;
 constexpr int NT_SOLVE = 1024;  // solver workgroup (one-image and batched kernels alike)
 
 // Setup of the solve (Alg. 1 initialisation): masses, the occupied levels A
@@ -2296,16 +2322,14 @@ __device__ uint64_t solve_setup(const uint32_t* hS, const uint32_t* hG, int64_t 
 }
 
 // Alg. 1 (Eqs. 11-15) for at most p.iters passes and the target histogram of
-// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global); gcells:
-// global scratch (gcap cells) for the class list when it does not fit in
-// LDS.  Writes illum/refl/target (counts, dense over the l levels) and the
+// Eqs. (17)-(20).  hS/hG: image and gradient histograms (global).  Writes
+// illum/refl/target (counts, dense over the l levels) and the
 // number of passes run when non-null, and with ckpt non-null and
 // p.ckpt_every > 0 the dense (L, R) of t = 0, every, 2 every, ... (2 l floats
 // each, see write_state).
 template <int BINS, int NT, int BUDGET, bool MAY_BE_EMPTY = true>
 __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
-                            SolveSmem<BINS, NT, BUDGET>& sm, typename CellT<BINS>::type* gcells, int64_t gcap,
-                            float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr,
+                            SolveSmem<BINS, NT, BUDGET>& sm, float* illum, float* refl, float* target, uint32_t* flags, float* ckpt = nullptr,
                             int32_t* passes_out = nullptr) {
   const int t = threadIdx.x;
   const uint64_t Ns = solve_setup<BINS, NT>(hS, hG, npix, sm, flags);
@@ -2325,15 +2349,13 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
   }
   int passes;
   if constexpr (BINS == 256) {
-    build_class_list<BINS, NT, BUDGET>(sm, gcells, gcap);
+    build_class_list<BINS, NT, BUDGET>(sm);
     if (!sm.use_list)
-      passes = iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
-    else if (!sm.cells_lds)
-      passes = iterate<BINS, NT, BUDGET, true, false, false>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, false, false>(sm, p, ckpt);
     else if (sm.tab_lds)
-      passes = iterate<BINS, NT, BUDGET, true, true, true>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, true, true>(sm, p, ckpt);
     else
-      passes = iterate<BINS, NT, BUDGET, true, true, false>(sm, gcells, p, ckpt);
+      passes = iterate<BINS, NT, BUDGET, true, false>(sm, p, ckpt);
   } else {
     if (t == 0) {
       sm.C = 0;
@@ -2343,7 +2365,7 @@ __device__ __forceinline__ void solve_image(const uint32_t* hS, const uint32_t* 
       sm.nBp = (nB + 3) & ~3;
     }
     __syncthreads();
-    passes = iterate<BINS, NT, BUDGET, false, false, false>(sm, gcells, p, ckpt);
+    passes = iterate<BINS, NT, BUDGET, false, false>(sm, p, ckpt);
   }
   if (passes_out && t == 0) *passes_out = passes;
 

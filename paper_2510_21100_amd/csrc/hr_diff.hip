@@ -39,16 +39,12 @@ constexpr double LOSS_SCALE = 4294967296.0;  // 2^32: fixed point of the squared
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(NT_SOLVE) void k_solve_ckpt(const uint32_t* hv, const uint32_t* hg, SolveParams p,
-                                                          int ncp, float* ckpt, float* target, uint32_t* lists,
-                                                          uint32_t* flags) {
+                                                          int ncp, float* ckpt, float* target, uint32_t* flags) {
   constexpr int BINS = DIFF_BINS;
   __shared__ SolveSmem<BINS, NT_SOLVE, SOLVE_BUDGET_PLAIN> sm;
   const int i = blockIdx.x;
-  using cell_t = typename CellT<BINS>::type;
   solve_image<BINS, NT_SOLVE, SOLVE_BUDGET_PLAIN>(
-      hv + (size_t)i * BINS, hg + (size_t)i * BINS, -1, p, sm,
-      reinterpret_cast<cell_t*>(lists + (size_t)i * LIST_WORDS<BINS>),
-      LIST_WORDS<BINS> * 4 / (int64_t)sizeof(cell_t), nullptr, nullptr, target + (size_t)i * BINS, flags,
+      hv + (size_t)i * BINS, hg + (size_t)i * BINS, -1, p, sm, nullptr, nullptr, target + (size_t)i * BINS, flags,
       ckpt + (size_t)i * ncp * 2 * BINS);
 }
 
@@ -494,8 +490,8 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
 namespace launch {
 
 hipError_t solve_ckpt(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, float* ckpt,
-                      float* target, uint32_t* lists, uint32_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_solve_ckpt, dim3(n), dim3(NT_SOLVE), 0, s, hv, hg, p, ncp, ckpt, target, lists, flags);
+                      float* target, uint32_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_ckpt, dim3(n), dim3(NT_SOLVE), 0, s, hv, hg, p, ncp, ckpt, target, flags);
   return hipGetLastError();
 }
 

@@ -56,12 +56,11 @@ template <int BITS> struct BatchBudget {
 
 template <int BINS, int NT>
 __global__ __launch_bounds__(NT) void k_solve(const uint32_t* hS, const uint32_t* hG, int64_t npix, SolveParams p,
-                                              uint32_t* lists, float* illum, float* refl, float* target,
+                                              float* illum, float* refl, float* target,
                                               int32_t* passes, uint32_t* flags) {
   __shared__ SolveSmem<BINS, NT, SOLVE_BUDGET_PLAIN> sm;
   solve_image<BINS, NT, SOLVE_BUDGET_PLAIN>(
-      hS, hG, npix, p, sm, reinterpret_cast<typename CellT<BINS>::type*>(lists),
-      (int64_t)LIST_WORDS<BINS> * 4 / (int64_t)sizeof(typename CellT<BINS>::type), illum, refl, target, flags,
+      hS, hG, npix, p, sm, illum, refl, target, flags,
       nullptr, passes);
 }
 
@@ -159,7 +158,7 @@ __global__ __launch_bounds__(NT_PIX) void k_hist_batch(const ImgDesc* __restrict
 // tables, so nothing of the item loop stays live across the solver.
 template <int BITS>
 __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
-                             int64_t st_words, int i, uint32_t* lists_base, int64_t lists_stride, uint32_t* flags,
+                             int64_t st_words, int i, uint32_t* flags,
                              BatchSmem<BITS>& sm, uint32_t* red) {
   constexpr int BINS = Cfg<BITS>::BINS;
   ImageState* s = state_of(st, st_words, i);
@@ -199,10 +198,7 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
   const BatchOut out = hdr->out;
   float* tgt = s->target(BINS);
   solve_image<BINS, NT_BATCH, BatchBudget<BITS>::value, false>(
-      lhs, lhg, npix, hdr->params, sm.solve,
-      reinterpret_cast<typename CellT<BINS>::type*>(lists_base + (int64_t)i * lists_stride),
-      lists_stride * 4 / (int64_t)sizeof(typename CellT<BINS>::type),
-      out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
+      lhs, lhg, npix, hdr->params, sm.solve, out.illum ? out.illum + (int64_t)slot * BINS : nullptr, out.refl ? out.refl + (int64_t)slot * BINS : nullptr,
       tgt, flags, nullptr, out.passes ? out.passes + slot : nullptr);
   drain_memory();
   __syncthreads();
@@ -220,7 +216,8 @@ __device__ void finish_image(BatchHeader* hdr, const ImgDesc* desc, ImgCounters*
   if (threadIdx.x == 0) {
     // append to the ready list: position by arrival, entry = image + 1
     const uint32_t pos = atomicAdd(&hdr->nready, 1u);
-    __hip_atomic_store(to_global(&ctr[pos].fifo), (uint32_t)i + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    fence_release_agent();  // the LUT is in memory before the entry can be seen
+    __hip_atomic_store(to_global(&ctr[pos].fifo), (uint32_t)i + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // zero the partial slots for the next call (no other workgroup touches them
   // now; their loads above have returned), after the image is published: the
@@ -279,8 +276,7 @@ __device__ inline void claim_remap(BatchHeader* hdr, const ImgDesc* desc, ImgCou
 
 template <int BITS>
 __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgDesc* __restrict__ desc,
-                                                    ImgCounters* ctr, ImageState* st, uint32_t* lists_base,
-                                                    int64_t lists_stride, uint32_t* flags) {
+                                                    ImgCounters* ctr, ImageState* st, uint32_t* flags) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ BatchSmem<BITS> sm;
   __shared__ uint32_t red[NT_BATCH / 64];
@@ -315,7 +311,7 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
       last_s = last ? 1u : 0u;
     }
     __syncthreads();
-    if (last_s) finish_image<BITS>(hdr, desc, ctr, st, st_words, i, lists_base, lists_stride, flags, sm, red);
+    if (last_s) finish_image<BITS>(hdr, desc, ctr, st, st_words, i, flags, sm, red);
     __syncthreads();
   }
   // Remap items, images in the order their LUTs were published, so that no
@@ -375,8 +371,7 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
 // the caller passes none, the descriptor table (header, descriptors, counters),
 // the per-image states (room for NOALLOC_MAX_IMAGES states of the larger,
 // 1024-level layout; a call strides them by the layout of its own level
-// count, as the batched kernel does), the solver's class-list scratch (256
-// levels only: 1024 levels never use it).
+// count, as the batched kernel does).
 constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 struct NoallocLayout {
   static constexpr int64_t FLAGS = 0;
@@ -385,12 +380,10 @@ struct NoallocLayout {
       sizeof(BatchHeader) + NOALLOC_MAX_IMAGES * (sizeof(ImgDesc) + sizeof(ImgCounters));
   static constexpr int64_t STATE = align256(TABLE + TABLE_BYTES);
   static constexpr int64_t STATE_WORDS = ImageState::words(1024);  // per image
-  static constexpr int64_t LISTS = align256(STATE + 4 * STATE_WORDS * NOALLOC_MAX_IMAGES);
-  static constexpr int64_t LIST_WORDS_256 = LIST_WORDS<256>;  // per image
-  static constexpr int64_t BYTES = align256(LISTS + 4 * LIST_WORDS_256 * NOALLOC_MAX_IMAGES);
+  static constexpr int64_t BYTES = align256(STATE + 4 * STATE_WORDS * NOALLOC_MAX_IMAGES);
 };
 
-// The scratch itself, about 3.6 MB on every GPU the library runs on, held
+// The scratch itself, about 0.5 MB on every GPU the library runs on, held
 // until the process ends.  Host code never passes this name to a kernel: it
 // is a host-side stand-in; the device address comes from hipGetSymbolAddress.
 static __device__ __align__(256) uint8_t scratch[NoallocLayout::BYTES];
@@ -459,15 +452,14 @@ hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, i
 }
 
 hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
-                 uint32_t* lists, float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags,
-                 hipStream_t s) {
+                 float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags, hipStream_t s) {
   // same workgroup shape as the batched kernel's solver: identical results
   if (bins == 256)
-    hipLaunchKernelGGL((k_solve<256, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
-                       refl, target, passes, flags);
+    hipLaunchKernelGGL((k_solve<256, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, illum, refl,
+                       target, passes, flags);
   else
-    hipLaunchKernelGGL((k_solve<1024, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, lists, illum,
-                       refl, target, passes, flags);
+    hipLaunchKernelGGL((k_solve<1024, NT_SOLVE>), dim3(1), dim3(NT_SOLVE), 0, s, hS, hG, npix, p, illum, refl,
+                       target, passes, flags);
   return hipGetLastError();
 }
 
@@ -499,13 +491,11 @@ hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lu
 
 
 hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
-                 uint32_t* lists, int64_t lists_stride, uint32_t* flags, hipStream_t s) {
+                 uint32_t* flags, hipStream_t s) {
   if (bits == 8)
-    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, lists_stride,
-                       flags);
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, flags);
   else
-    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, lists_stride,
-                       flags);
+    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, flags);
   return hipGetLastError();
 }
 
@@ -563,7 +553,6 @@ hipError_t batch_noalloc(int bits, int grid_per_cu, const NoallocTable& t, uint3
   auto* ctr = reinterpret_cast<ImgCounters*>(base + NoallocLayout::TABLE + sizeof(BatchHeader) +
                                              NOALLOC_MAX_IMAGES * sizeof(ImgDesc));
   auto* st = reinterpret_cast<ImageState*>(base + NoallocLayout::STATE);
-  auto* lists = reinterpret_cast<uint32_t*>(base + NoallocLayout::LISTS);
   uint32_t* flags = flags_user ? flags_user : reinterpret_cast<uint32_t*>(base + NoallocLayout::FLAGS);
   // the kernels stride the states by words(bins) of the call's level count
   static_assert(NoallocLayout::STATE_WORDS >= ImageState::words(256), "state layout");
@@ -571,13 +560,11 @@ hipError_t batch_noalloc(int bits, int grid_per_cu, const NoallocTable& t, uint3
   if (bits == 8) {
     hipLaunchKernelGGL(k_noalloc_setup<8>, dim3(16), dim3(256), 0, s, t, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists,
-                       (int64_t)LIST_WORDS<256>, flags);
+    hipLaunchKernelGGL(k_batch<8>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, flags);
   } else {
     hipLaunchKernelGGL(k_noalloc_setup<10>, dim3(16), dim3(256), 0, s, t, base);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, lists, (int64_t)0,
-                       flags);
+    hipLaunchKernelGGL(k_batch<10>, dim3(grid), dim3(NT_BATCH), 0, s, hdr, desc, ctr, st, flags);
   }
   return hipGetLastError();
 }

@@ -116,14 +116,13 @@ hipError_t hist(int bits, const ImgDesc& d, int64_t tile_px, uint32_t* hs, uint3
 hipError_t hist_batch(int bits, int n, const ImgDesc* desc, int64_t max_tiles, int64_t tile_px, uint32_t* hs,
                       uint32_t* hg, ImageState* st, uint32_t* flags, hipStream_t s);
 hipError_t solve(int bins, const uint32_t* hS, const uint32_t* hG, int64_t npix, const SolveParams& p,
-                 uint32_t* lists, float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags,
-                 hipStream_t s);
+                 float* illum, float* refl, float* target, int32_t* passes, uint32_t* flags, hipStream_t s);
 hipError_t equalize_lut(int bins, const uint32_t* hS, uint16_t* lut, uint16_t* lut_user, hipStream_t s);
 hipError_t lut(int bins, const uint32_t* hS, const float* target, uint16_t* lut, uint16_t* lut_user,
                hipStream_t s);
 hipError_t remap(int bits, const ImgDesc& d, int64_t tile_px, const uint16_t* lut, hipStream_t s);
 hipError_t batch(int bits, int grid, BatchHeader* hdr, const ImgDesc* desc, ImgCounters* ctr, ImageState* st,
-                 uint32_t* lists, int64_t lists_stride, uint32_t* flags, hipStream_t s);
+                 uint32_t* flags, hipStream_t s);
 // persistent workgroups of the batched kernel one CU can hold (its LDS and
 // registers allow), 0 on a query failure
 int batch_max_wg_per_cu(int bits);
@@ -132,7 +131,7 @@ int batch_step_px(int bits);
 int max_width(int bits);
 // differentiated form (256 levels)
 hipError_t solve_ckpt(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, float* ckpt,
-                      float* target, uint32_t* lists, uint32_t* flags, hipStream_t s);
+                      float* target, uint32_t* flags, hipStream_t s);
 hipError_t softmatch(int n, const ImgDesc* desc, int64_t max_npix, const uint32_t* hv, const float* target,
                      float* m_tab, unsigned long long* acc, double* loss, float* dtarget, hipStream_t s);
 hipError_t solve_vjp(int n, const uint32_t* hv, const uint32_t* hg, const SolveParams& p, int ncp, const float* ckpt,

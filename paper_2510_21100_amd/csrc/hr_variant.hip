@@ -99,6 +99,9 @@ __global__ __launch_bounds__(256) void k_hist_variant(ImgDesc d, int64_t tile_px
     if (k < BINS && lhs[k]) atomicAdd(&hs[k], lhs[k]);
     if (lg[k]) atomicAdd(&graw[k], lg[k]);
   }
+  // every wave's merge atomics are performed before thread 0 releases
+  drain_memory();
+  __syncthreads();
   if (threadIdx.x == 0) {
     if (clamped_any) atomicOr(flags, FLAG_VALUE_CLAMPED);
     fence_release_agent();

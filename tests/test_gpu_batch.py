@@ -47,6 +47,38 @@ def test_batch_equals_plain_8bit(H):
     _compare_to_plain(H, imgs, [to_gpu(x) for x in imgs], H.Params(bins=256))
 
 
+def test_batch_fresh_workspaces(H):
+    """Batches on freshly created workspaces (their LUT memory never written):
+    a remap that read an image's LUT before the finishing workgroup's stores
+    reached memory would produce zeros.  Every call equals the one-image path."""
+    params = H.Params(bins=256)
+    for shapes in (SHAPES[:5], SHAPES):
+        imgs = _batch_imgs(shapes)
+        gimgs = [to_gpu(x) for x in imgs]
+        ref = []
+        for g in gimgs:
+            o, _ = H.enhance(g, params)
+            ref.append(o)
+        torch.cuda.synchronize()
+        for rep in range(16):
+            ws = H.Workspace(max_images=8, max_bins=1024)
+            outs, _ = H.enhance_batch(gimgs, params, ws=ws)
+            torch.cuda.synchronize()
+            for i, (a, b) in enumerate(zip(outs, ref)):
+                assert torch.equal(a, b), (len(shapes), rep, i)
+            ws.close()
+
+
+def test_batch_equals_plain_bright_8bit(H):
+    """Bright images take the solver's other forms (no class tables, running
+    sums past 40 000 occupied cells): batched still equals one-image."""
+    rng = np.random.default_rng(13)
+    imgs = [make_image(config_seed(3, 3, i), h, w, bits=8, ceil=c)
+            for i, (h, w, c) in enumerate([(300, 400, 0.9), (240, 320, 1.0), (100, 700, 0.8)])]
+    imgs.append(rng.integers(0, 256, size=(150, 200, 3), dtype=np.uint8))
+    _compare_to_plain(H, imgs, [to_gpu(x) for x in imgs], H.Params(bins=256))
+
+
 def test_batch_equals_plain_10bit(H):
     shapes = [(216, 384), (61, 700), (400, 33)]
     imgs = _batch_imgs(shapes, bits=10, cfg=4)

@@ -150,6 +150,22 @@ def test_solve_parity_10bit_all_levels(H):
     assert e[0] <= REL_TOL and e[1] <= REL_TOL and e[2] <= 10 * REL_TOL
 
 
+@pytest.mark.parametrize("ceil,form", [(0.9, "class list, classes computed in the sweeps"),
+                                       (1.0, "running sums (more than 40 000 occupied cells)"),
+                                       (None, "running sums, every level occupied")])
+def test_solve_parity_8bit_many_cells(H, ceil, form):
+    # bright 8-bit images: the forms the solver takes past the low-light range
+    if ceil is None:
+        img = np.random.default_rng(12).integers(0, 256, size=(192, 256, 3), dtype=np.uint8)
+    else:
+        img = cfg_image(2, 300, 400, ceil=ceil)
+    hS, _, _, hG = oracle_hists(img, 256)
+    print(form, "occupied cells", int((hS > 0).sum()) * int((hG > 0).sum()))
+    e = _solve_case(H, img, O.Params(bins=256, iters=50))
+    print("rel err illum %.2e refl %.2e target %.2e" % e)
+    assert e[0] <= REL_TOL and e[1] <= REL_TOL and e[2] <= 10 * REL_TOL
+
+
 @pytest.mark.parametrize("iters", [0, 1, 3])
 def test_solve_few_iterations_10bit(H, iters):
     img = cfg_image(4, 90, 120, bits=10)
