@@ -361,6 +361,17 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
     lds_wait();  // every wave is done with item_s and the table before they change
     bare_barrier();
   }
+  // The last workgroup to leave puts the cursors and the per-image counters
+  // back to zero (every other workgroup has made its last access to them
+  // before its count): the next launch with the same descriptor table finds
+  // them as an upload would leave them.
+  if (threadIdx.x == 0 && atomicAdd(&hdr->exited, 1u) == gridDim.x - 1) {
+    for (int k = 0; k < nimg; ++k) ctr[k] = ImgCounters{0u, 0u, 0u, 0u};
+    hdr->next = 0u;
+    hdr->rhead = 0u;
+    hdr->nready = 0u;
+    hdr->exited = 0u;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,7 @@ struct BatchHeader {
   int32_t n;             // images in this call
   int32_t total_tiles;   // histogram items over all images
   uint32_t nready;       // images in the ready list
+  uint32_t exited;       // workgroups that have left the kernel (the last resets the cursors)
   int64_t tile_px;       // pixels per histogram item (multiple of the pixel step)
   int64_t rtile_px;      // pixels per remap item (multiple of the pixel step)
   SolveParams params;

@@ -47,6 +47,30 @@ def test_batch_equals_plain_8bit(H):
     _compare_to_plain(H, imgs, [to_gpu(x) for x in imgs], H.Params(bins=256))
 
 
+def test_batch_repeated_unchanged_table(H):
+    """Calls with an unchanged descriptor table skip its upload: the previous
+    launch's last workgroup has put the cursors and counters back to zero.
+    Repeats, changes and returns, with the outputs cleared before each call."""
+    ws = H.Workspace(max_images=8, max_bins=1024)
+    params = H.Params(bins=256)
+    a = [to_gpu(x) for x in _batch_imgs(SHAPES[:5])]
+    b = [to_gpu(x) for x in _batch_imgs(SHAPES[2:7])]
+    refs = {}
+    for name, g in (("a", a), ("b", b)):
+        refs[name] = [H.enhance(x, params)[0] for x in g]
+    torch.cuda.synchronize()
+    outs = {"a": [torch.empty_like(x) for x in a], "b": [torch.empty_like(x) for x in b]}
+    for k, name in enumerate("aaabbaab"):
+        g = a if name == "a" else b
+        for o in outs[name]:
+            o.zero_()
+        H.enhance_batch(g, params, outs=outs[name], ws=ws)
+        torch.cuda.synchronize()
+        for i, (x, y) in enumerate(zip(outs[name], refs[name])):
+            assert torch.equal(x, y), (k, name, i)
+    ws.close()
+
+
 def test_batch_fresh_workspaces(H):
     """Batches on freshly created workspaces (their LUT memory never written):
     a remap that read an image's LUT before the finishing workgroup's stores
