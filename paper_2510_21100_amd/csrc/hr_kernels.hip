@@ -97,11 +97,12 @@ template <int BITS>
 __global__ __launch_bounds__(NT_PIX) void k_remap(ImgDesc d, int64_t tile_px, const uint16_t* lut) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ float2 tab[BINS];
+  __shared__ uint32_t stage[NT_PIX * Pix<BITS, NT_PIX>::NW];
   load_remap_table<BINS, NT_PIX>(lut, tab);
   __syncthreads();
   const int64_t P0 = (int64_t)blockIdx.x * tile_px;
   const int64_t P1 = min(P0 + tile_px, d.npix);
-  remap_tile<BITS, NT_PIX>(d, P0, P1, tab);
+  remap_tile<BITS, NT_PIX>(d, P0, P1, tab, stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -113,7 +114,10 @@ union BatchSmem {
   HistSmem<BITS, NT_BATCH> hist;
   SolveSmem<Cfg<BITS>::BINS, NT_BATCH, BatchBudget<BITS>::value> solve;
   LutSmem<Cfg<BITS>::BINS, NT_BATCH> lut;
-  float2 tab[Cfg<BITS>::BINS];
+  struct {
+    float2 tab[Cfg<BITS>::BINS];                     // remap table of the current image
+    uint32_t stage[NT_BATCH * Pix<BITS, NT_BATCH>::NW];  // staged stores of the remap
+  } rm;
 };
 
 
@@ -349,7 +353,7 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
         const uint32_t L = __hip_atomic_load(to_global(reinterpret_cast<const uint32_t*>(lut)) + (v >> 1),
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t lv = (v & 1) ? (L >> 16) : (L & 0xffffu);
-        sm.tab[v] = remap_entry((uint32_t)v, lv);
+        sm.rm.tab[v] = remap_entry((uint32_t)v, lv);
       }
       lds_wait();
       bare_barrier();
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(NT_BATCH) void k_batch(BatchHeader* hdr, const ImgD
     }
     const int64_t P0 = (int64_t)tile * rtile_px;
     const int64_t P1 = min(P0 + rtile_px, d.npix);
-    remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.tab);
+    remap_tile<BITS, NT_BATCH>(d, P0, P1, sm.rm.tab, sm.rm.stage);
     lds_wait();  // every wave is done with item_s and the table before they change
     bare_barrier();
   }
