@@ -97,7 +97,7 @@ template <int BITS>
 __global__ __launch_bounds__(NT_PIX) void k_remap(ImgDesc d, int64_t tile_px, const uint16_t* lut) {
   constexpr int BINS = Cfg<BITS>::BINS;
   __shared__ float2 tab[BINS];
-  __shared__ uint32_t stage[NT_PIX * Pix<BITS, NT_PIX>::NW];
+  __shared__ uint32_t stage[NT_PIX * 12];
   load_remap_table<BINS, NT_PIX>(lut, tab);
   __syncthreads();
   const int64_t P0 = (int64_t)blockIdx.x * tile_px;
@@ -116,7 +116,7 @@ union BatchSmem {
   LutSmem<Cfg<BITS>::BINS, NT_BATCH> lut;
   struct {
     float2 tab[Cfg<BITS>::BINS];                     // remap table of the current image
-    uint32_t stage[NT_BATCH * Pix<BITS, NT_BATCH>::NW];  // staged stores of the remap
+    uint32_t stage[NT_BATCH * 12];      // staged stores of the remap (48-byte chunks)
   } rm;
 };
 
