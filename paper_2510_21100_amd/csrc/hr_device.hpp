@@ -1026,35 +1026,23 @@ __device__ void remap_pixels(const ImgDesc& d, int64_t p, int n, const float2* t
   }
 }
 
-// Writes a wave's chunks (lane l holds the NW dwords of pixels pw + l PX ..,
-// consecutive in memory from out_wave) through the wave's LDS stage `sw`
-// (64 NW dwords): the chunks go to the stage in lane order and come back in
-// groups of NW / 3 dwords, so that each store instruction writes one
-// contiguous stretch of 64 groups (0.5 or 1 KB) instead of a group every
-// chunk.  LDS accesses of one wave complete in order, so the wave barriers
-// (which keep the compiler from reordering them) are the only waits.
-template <int NW>
-__device__ inline void store_wave_staged(uint8_t* out_wave, const uint32_t (&o)[NW], uint32_t* sw) {
+// Writes a wave's 48-byte chunks (lane l holds the 12 dwords of pixels
+// pw + l PX .., consecutive in memory from out_wave) through the wave's LDS
+// stage `sw` (64 x 12 dwords): the chunks go to the stage in lane order and
+// come back 16 bytes at a time, so that each store instruction writes one
+// contiguous 1 KB stretch instead of 16 bytes every 48.  LDS accesses of one
+// wave complete in order, so the wave barriers (which keep the compiler from
+// reordering them) are the only waits.
+__device__ inline void store_wave_staged(uint8_t* out_wave, const uint32_t (&o)[12], uint32_t* sw) {
   const int lane = threadIdx.x & 63;
-  if constexpr (NW == 6) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) *reinterpret_cast<v2u*>(sw + lane * 6 + 2 * q) = v2u{o[2 * q], o[2 * q + 1]};
-    __builtin_amdgcn_wave_barrier();
-    const gptr<v2u> dst = to_global(reinterpret_cast<v2u*>(out_wave));
+  for (int q = 0; q < 3; ++q)
+    *reinterpret_cast<v4u*>(sw + lane * 12 + 4 * q) = v4u{o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]};
+  __builtin_amdgcn_wave_barrier();
+  const gptr<v4u> dst = to_global(reinterpret_cast<v4u*>(out_wave));
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-      __builtin_nontemporal_store(*reinterpret_cast<const v2u*>(sw + 2 * (lane + 64 * q)), dst + lane + 64 * q);
-  } else {
-    static_assert(NW == 12, "chunk of 24 or 48 bytes");
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      *reinterpret_cast<v4u*>(sw + lane * 12 + 4 * q) = v4u{o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]};
-    __builtin_amdgcn_wave_barrier();
-    const gptr<v4u> dst = to_global(reinterpret_cast<v4u*>(out_wave));
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(sw + 4 * (lane + 64 * q)), dst + lane + 64 * q);
-  }
+  for (int q = 0; q < 3; ++q)
+    __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(sw + 4 * (lane + 64 * q)), dst + lane + 64 * q);
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -1097,7 +1085,7 @@ __device__ void remap_tile(const ImgDesc& d, int64_t P0, int64_t P1, const float
           if (pf + PX <= P1) load_words<NW>(d.in + pf * CB, buf[k]);
           const int64_t pw = p - (int64_t)lane * PX;  // the wave's first pixel
           if (pw + 64 * PX <= P1)  // every chunk of the wave is full
-            store_wave_staged<NW>(d.out + pw * CB, o, sw);
+            store_wave_staged(d.out + pw * CB, o, sw);
           else
             store_words_nt<NW>(d.out + p * CB, o);
         } else {
