@@ -1666,9 +1666,12 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
     sm.bq[q] = q < nB ? (float)sm.B[q] / (float)(BINS - 1) : 0.f;
   }
   __syncthreads();
+  // the lanes of a class are consecutive: the cells of the class's lanes
+  // before this one are a difference of two block prefix sums
+  block_scan<NT, int32_t>(sm.lane_cells, NT, sm.redi);
   int before = 0;
   if (cl.q >= 0) {
-    for (int x = t - cl.k; x < t; ++x) before += sm.lane_cells[x];
+    before = sm.lane_cells[t] - sm.lane_cells[t - cl.k];
     if (cl.k == cl.g - 1) sm.csz[mcls] = before + mine;
   }
   __syncthreads();
@@ -1722,17 +1725,12 @@ __device__ __forceinline__ void build_class_list(SolveSmem<BINS, NT, BUDGET>& sm
         int pad = 0;
         for (int guard = 0; guard <= 64; ++guard) {
           const int w = nv + pad;
-          int incl = w;
-#pragma unroll
-          for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += y;
-          }
+          const int incl = wave_scan(w);
           offs[q] = pos + incl - nv;  // start of this class after its padding
           const bool straddle = nv > 0 && (offs[q] & 63) + nv > 64;
           const uint64_t mask = __ballot(straddle);
           if (!mask) {
-            pos += __shfl(incl, 63, 64);
+            pos += read_lane(incl, 63);
             break;
           }
           if (lane == (int)__builtin_ctzll(mask)) pad += 64 - (offs[q] & 63);
