@@ -389,7 +389,7 @@ def batched_line(H, tune, name, imgs, bits, args, dev, with_plain: bool):
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": measured_traffic(name, bits),
-            "kernel": f"k_batch<{bits}> (graph: descriptor copy + persistent kernel)",
+            "kernel": f"k_batch<{bits}> (persistent kernel; the descriptor copy only when the table changes)",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
         },
@@ -622,7 +622,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "form": "batched: one persistent launch per step, replayed from a captured HIP graph",
+            "form": "batched: one persistent launch per step (a captured HIP graph with the descriptor copy when the table changes, the kernel alone when it repeats)",
             "images": head["images"],
             "pixels": head["pixels"],
             "bins": head["bins"],
