@@ -1257,8 +1257,9 @@ __device__ inline int class_of(int a, int b) {
 // B (jlo = jhi: empty).  Both bounds (2m +- 1)(l-1) / 2a are odd multiples of
 // l-1 over an even number, so they lie at least 1/2a from an integer, and
 // below 1.5 (l-1); the FP32 product with the rounded reciprocal 1/2a is within
-// 2^-23 relative, under 2e-4, so truncation gives the exact floors (checked
-// for every a and m <= a at l = 256 and 1024).
+// 2^-23 relative, under 2e-4, so truncation gives the exact floors.  The lower
+// bound's + 1 goes into the same FMA (one more rounding of at most 2^-13 below
+// 2^11): still exact (checked for every a and m <= a at l = 256 and 1024).
 template <int BINS, typename SM>
 __device__ inline void class_run_upper(const SM& sm, int i, int m, int& jlo, int& jhi) {
   constexpr uint32_t D = BINS - 1;
@@ -1269,7 +1270,7 @@ __device__ inline void class_run_upper(const SM& sm, int i, int m, int& jlo, int
     return;
   }
   const float inv = sm.inv2a[i];
-  const uint32_t blo = m == 0 ? 0u : (uint32_t)((float)((2u * m - 1u) * D) * inv) + 1u;
+  const uint32_t blo = m == 0 ? 0u : (uint32_t)fmaf((float)((2u * m - 1u) * D), inv, 1.f);
   const uint32_t bhi = min((uint32_t)((float)((2u * m + 1u) * D) * inv), (uint32_t)(BINS - 1));
   jlo = sm.PB[blo];
   jhi = sm.PB[max(bhi + 1u, blo)];  // blo > bhi: empty
@@ -2042,7 +2043,8 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
         // A lane takes CK consecutive classes m0 .. m0 + CK - 1 on its rows:
         // on row a the runs of the classes are [E(m), E(m + 1)) with
         // E(m) = floor((2m - 1)(l-1) / 2a) + 1 (capped at l, E(0) = 0), the
-        // lower bound of class_run_upper, so CK + 1 bounds and running-sum
+        // lower bound of class_run_upper (one FMA and a truncation), so CK + 1
+        // bounds and running-sum
         // reads give the CK runs.  Classes above a get E = l on both ends, an
         // exact zero.  Two rows per step, each stage's LDS reads issued
         // together.
@@ -2073,7 +2075,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
             for (int x = 0; x < 2; ++x)
 #pragma unroll
               for (int w = 0; w <= CK; ++w) {
-                const uint32_t e = (m0 + w) ? min((uint32_t)(num[w] * inv[x]) + 1u, (uint32_t)BINS) : 0u;
+                const uint32_t e = (m0 + w) ? min((uint32_t)fmaf(num[w], inv[x], 1.f), (uint32_t)BINS) : 0u;
                 r[x][w] = sm.rcum[e];
               }
             __builtin_amdgcn_sched_barrier(0);
@@ -2090,7 +2092,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
             double r[CK + 1];
 #pragma unroll
             for (int w = 0; w <= CK; ++w) {
-              const uint32_t e = (m0 + w) ? min((uint32_t)(num[w] * inv) + 1u, (uint32_t)BINS) : 0u;
+              const uint32_t e = (m0 + w) ? min((uint32_t)fmaf(num[w], inv, 1.f), (uint32_t)BINS) : 0u;
               r[w] = sm.rcum[e];
             }
 #pragma unroll

@@ -7,10 +7,11 @@ the exact integer forms:
     plus 2^23, rounded once to FP32 (one fused multiply-add), whose low
     mantissa bits are then the class;
   * the run of reflectance levels of class m on illumination row a (class
-    list, 1024-level class totals, reverse pass): the FP32 product
-    float32((2m +- 1)(l-1)) * float32(1 / (2a)), truncated, gives the lower
-    bound E(m) = floor((2m-1)(l-1) / 2a) + 1 (capped at l) and the upper
-    bound floor((2m+1)(l-1) / 2a) (capped at l-1).
+    list, 1024-level class totals, reverse pass): the FP32 fused multiply-add
+    float32((2m-1)(l-1)) * float32(1 / (2a)) + 1, rounded once and truncated,
+    gives the lower bound E(m) = floor((2m-1)(l-1) / 2a) + 1 (capped at l);
+    the FP32 product float32((2m+1)(l-1)) * float32(1 / (2a)), truncated,
+    gives the upper bound floor((2m+1)(l-1) / 2a) (capped at l-1).
 
 The exact references are integer arithmetic only (no oracle code).
 """
@@ -54,9 +55,12 @@ def _fp32_run_bounds(levels: int, a: int, m: np.ndarray):
     inv = np.float32(1.0) / np.float32(2 * a)  # IEEE FP32 division
     lo_num = ((2 * m - 1) * D).astype(np.float32)  # exact: below 2^24
     hi_num = ((2 * m + 1) * D).astype(np.float32)
-    lo = np.floor((lo_num * inv).astype(np.float64)).astype(np.int64)  # truncation of a positive float
+    # fmaf(lo_num, inv, 1): the exact product plus 1 (exact in float64: at most
+    # 46 significant bits below 2^22), rounded once to FP32, then truncated
+    lo_fma = (lo_num.astype(np.float64) * np.float64(inv) + 1.0).astype(np.float32)
+    lo1 = np.floor(lo_fma.astype(np.float64)).astype(np.int64)  # truncation of a positive float
     hi = np.floor((hi_num * inv).astype(np.float64)).astype(np.int64)
-    E = np.where(m == 0, 0, np.minimum(lo + 1, levels))
+    E = np.where(m == 0, 0, np.minimum(lo1, levels))
     upper = np.minimum(hi, levels - 1)
     return E, upper
 
