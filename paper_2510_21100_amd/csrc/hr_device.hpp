@@ -1214,7 +1214,12 @@ struct SolveCore {
   alignas(16) float bq[BINS + PAD];                 // levels b of B over (l-1), FP32 (zero padded)
   float lraw[BINS + 4];                             // L' of Eq. (12) on A, before Eq. (15); [n] = 0
   float rn[BINS + 4];                               // R' of Eq. (13) on B, before Eq. (14); [n] = 0
-  double rcum[BINS + 1];                            // running sums of R by level (sweeps without a list)
+  // running sums of R by level (class totals without a list).  At 1024 levels
+  // the entries past l repeat the total, up to the largest run bound a class
+  // group reaches (E(4) on row a = 1: floor(7 (l-1) / 2) + 1 = 3581), so the
+  // bounds need no clamp to l.
+  static constexpr int RCUM = BINS == 1024 ? 7 * (BINS - 1) / 2 + 2 : BINS + 1;
+  double rcum[RCUM];
   float sd[BINS];                                   // s by level (dense)
   float inv2a[BINS];                                // 1 / (2a) for the rows of A
   alignas(8) float rho[BINS + 4];                   // s_m / d_m by class
@@ -1880,6 +1885,17 @@ __device__ inline void write_state(const SolveCore<BINS, NT>& sm, float* state, 
 // the next pass's class sweep, which is where the new L and R meet the old
 // ones: the changes of pass t are summed there, in pass t + 1, and the
 // decision (the same bits in every lane) is taken after its barrier.
+// Index of the running sums for the lower run bound x = (2m-1)(l-1)/2a + 1
+// computed in FP32: truncated, and clamped to l where the sums are not padded
+// past it (256 levels).
+template <int BINS>
+__device__ __forceinline__ uint32_t run_bound(float x) {
+  if constexpr (BINS == 1024)
+    return (uint32_t)x;
+  else
+    return min((uint32_t)x, (uint32_t)BINS);
+}
+
 template <int BINS, int NT, int BUDGET, bool LIST, bool TAB>
 __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const SolveParams& p, float* ckpt) {
   using cell_t = typename CellT<BINS>::type;
@@ -2040,6 +2056,11 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
         }
         __syncthreads();
         block_scan<NT, double>(sm.rcum, BINS + 1, sm.redd);
+        if constexpr (BINS == 1024) {
+          constexpr int RCUM = SolveCore<BINS, NT>::RCUM;
+          for (int b = BINS + 1 + t; b < RCUM; b += NT) sm.rcum[b] = sm.rcum[BINS];
+          __syncthreads();
+        }
         // A lane takes CK consecutive classes m0 .. m0 + CK - 1 on its rows:
         // on row a the runs of the classes are [E(m), E(m + 1)) with
         // E(m) = floor((2m - 1)(l-1) / 2a) + 1 (capped at l, E(0) = 0), the
@@ -2075,7 +2096,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
             for (int x = 0; x < 2; ++x)
 #pragma unroll
               for (int w = 0; w <= CK; ++w) {
-                const uint32_t e = (m0 + w) ? min((uint32_t)fmaf(num[w], inv[x], 1.f), (uint32_t)BINS) : 0u;
+                const uint32_t e = (m0 + w) ? run_bound<BINS>(fmaf(num[w], inv[x], 1.f)) : 0u;
                 r[x][w] = sm.rcum[e];
               }
             __builtin_amdgcn_sched_barrier(0);
@@ -2092,7 +2113,7 @@ __device__ __forceinline__ int iterate(SolveSmem<BINS, NT, BUDGET>& sm, const So
             double r[CK + 1];
 #pragma unroll
             for (int w = 0; w <= CK; ++w) {
-              const uint32_t e = (m0 + w) ? min((uint32_t)fmaf(num[w], inv, 1.f), (uint32_t)BINS) : 0u;
+              const uint32_t e = (m0 + w) ? run_bound<BINS>(fmaf(num[w], inv, 1.f)) : 0u;
               r[w] = sm.rcum[e];
             }
 #pragma unroll

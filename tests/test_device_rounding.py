@@ -90,3 +90,24 @@ def test_run_bounds_reproduce_the_class_map(levels):
         E, _ = _fp32_run_bounds(levels, a, m)
         cls = np.searchsorted(E, b, side="right") - 1
         assert np.array_equal(cls, (2 * a * b + D) // (2 * D)), a
+
+
+def test_uncapped_run_bounds_stay_in_the_padded_sums():
+    """At 1024 levels the class totals read the running sums of R at E(m)
+    without clamping to l: the sums repeat their total up to index
+    7 (l-1) / 2 + 1.  Every bound a class group evaluates (classes
+    4q .. 4q + 4 on the rows a >= max(4q, 1)) lies inside that range."""
+    levels = 1024
+    D = levels - 1
+    rcum_len = 7 * D // 2 + 2
+    worst = 0
+    for a in range(1, levels):
+        inv = np.float32(1.0) / np.float32(2 * a)
+        q = np.arange(0, a // 4 + 1, dtype=np.int64)
+        m = (4 * q[:, None] + np.arange(5, dtype=np.int64)[None, :]).ravel()
+        m = m[m > 0]
+        num = ((2 * m - 1) * D).astype(np.float32)
+        e = np.floor((num.astype(np.float64) * np.float64(inv) + 1.0).astype(np.float32).astype(np.float64))
+        worst = max(worst, int(e.max()))
+    assert worst < rcum_len, worst
+    assert worst == rcum_len - 1  # the padding is as long as it needs to be
