@@ -106,9 +106,40 @@ __global__ __launch_bounds__(DIFF_BINS) void k_softmap(const uint32_t* hv, const
 // pixel pass: loss and the weighted level histogram G
 // ---------------------------------------------------------------------------
 
+// One pixel of the loss pass: its squared errors into sq (channels in order)
+// and its G term, in 2^-24 units, into the lane's run of equal levels; a run
+// goes to the level's LDS counter when the level changes (integer sums, so
+// the totals do not depend on how the pixels are grouped).
+template <typename TP>
+__device__ __forceinline__ void soft_pixel(uint32_t c0, uint32_t c1, uint32_t c2, TP tp, const float* scale,
+                                           float black, float& sq, int& cur, long long& run,
+                                           unsigned long long* g_lds) {
+  const uint32_t V = umax3(c0, c1, c2);
+  const float s = scale[V];
+  float gsum = 0.f;
+  const uint32_t cc[3] = {c0, c1, c2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float o = V ? (float)cc[c] * s : black;
+    const float e = o - tp[c];
+    sq = fmaf(e, e, sq);
+    gsum = fmaf(e, V ? (float)cc[c] : 1.f, gsum);
+  }
+  const long long gq = __double2ll_rn((double)gsum * G_SCALE);
+  if ((int)V != cur) {
+    if (cur >= 0 && run) atomicAdd(&g_lds[cur], (unsigned long long)run);
+    cur = (int)V;
+    run = 0;
+  }
+  run += gq;
+}
+
 // One workgroup per (tile, image); desc[i].in is the image, desc[i].out the
 // FP32 HWC target image (tight rows), acc[i] holds BINS int64 sums of G in
-// 2^-24 units followed by the squared-error sum in 2^-32 units.
+// 2^-24 units followed by the squared-error sum in 2^-32 units.  A lane takes
+// PX consecutive pixels per step; on tight, 16-byte aligned images their 48
+// bytes of RGB and 192 bytes of target come in as 16-byte loads, otherwise
+// pixel by pixel through the row stride.
 __global__ __launch_bounds__(NT_PIX) void k_softloss(const ImgDesc* desc, const float* m_tab, int64_t tile_px,
                                                      unsigned long long* acc) {
   constexpr int BINS = DIFF_BINS;
@@ -129,31 +160,53 @@ __global__ __launch_bounds__(NT_PIX) void k_softloss(const ImgDesc* desc, const 
   __syncthreads();
   const float black = mt[0] / (float)(BINS - 1);
   const gptr<const float> tg = to_global(reinterpret_cast<const float*>(d.out));
+  // p below is a multiple of PX (tile_px is), so a full step of a tight
+  // image starts 16-byte aligned in both arrays
+  const bool vec = d.in_vec && (reinterpret_cast<uintptr_t>(d.out) & 15u) == 0;
   float sq = 0.f;
+  int cur = -1;
+  long long run = 0;
   for (int64_t p = P0 + (int64_t)t * PX; p < P1; p += (int64_t)NT_PIX * PX) {
     const int n = (int)min((int64_t)PX, P1 - p);
-    for (int k = 0; k < n; ++k) {
-      const int64_t q = p + k;
-      const int64_t y = q / d.W;
-      const int x = (int)(q - y * d.W);
-      const gptr<const uint8_t> px = to_global(d.in + y * d.in_stride) + 3 * x;
-      const uint32_t c0 = px[0], c1 = px[1], c2 = px[2];
-      const uint32_t V = umax3(c0, c1, c2);
-      const float s = scale[V];
-      const gptr<const float> tp = tg + 3 * q;
-      float gsum = 0.f;
-      const uint32_t cc[3] = {c0, c1, c2};
+    if (vec && n == PX) {
+      const gptr<const v4u> src = to_global(reinterpret_cast<const v4u*>(d.in + 3 * p));
+      const gptr<const v4u> tsrc = to_global(reinterpret_cast<const v4u*>(d.out + 12 * p));
+      uint32_t w[12];
+      float tv[48];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float o = V ? (float)cc[c] * s : black;
-        const float e = o - tp[c];
-        sq = fmaf(e, e, sq);
-        gsum = fmaf(e, V ? (float)cc[c] : 1.f, gsum);
+      for (int q = 0; q < 3; ++q) {
+        const v4u a = src[q];
+        w[4 * q] = a.x;
+        w[4 * q + 1] = a.y;
+        w[4 * q + 2] = a.z;
+        w[4 * q + 3] = a.w;
       }
-      const long long gq = __double2ll_rn((double)gsum * G_SCALE);
-      atomicAdd(&g_lds[V], (unsigned long long)gq);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) {
+        const v4u b = tsrc[q];
+        tv[4 * q] = __uint_as_float(b.x);
+        tv[4 * q + 1] = __uint_as_float(b.y);
+        tv[4 * q + 2] = __uint_as_float(b.z);
+        tv[4 * q + 3] = __uint_as_float(b.w);
+      }
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        const uint32_t c0 = (w[(3 * k) >> 2] >> (8 * ((3 * k) & 3))) & 0xffu;
+        const uint32_t c1 = (w[(3 * k + 1) >> 2] >> (8 * ((3 * k + 1) & 3))) & 0xffu;
+        const uint32_t c2 = (w[(3 * k + 2) >> 2] >> (8 * ((3 * k + 2) & 3))) & 0xffu;
+        soft_pixel(c0, c1, c2, tv + 3 * k, scale, black, sq, cur, run, g_lds);
+      }
+    } else {
+      for (int k = 0; k < n; ++k) {
+        const int64_t q = p + k;
+        const int64_t y = q / d.W;
+        const int x = (int)(q - y * d.W);
+        const gptr<const uint8_t> px = to_global(d.in + y * d.in_stride) + 3 * x;
+        soft_pixel(px[0], px[1], px[2], tg + 3 * q, scale, black, sq, cur, run, g_lds);
+      }
     }
   }
+  if (cur >= 0 && run) atomicAdd(&g_lds[cur], (unsigned long long)run);
   const float tot = block_sum<NT_PIX>(sq, red);
   __syncthreads();
   unsigned long long* out = acc + (size_t)i * (BINS + 1);
