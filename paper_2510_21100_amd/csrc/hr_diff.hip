@@ -60,6 +60,8 @@ struct SoftSmem {
   uint64_t redu[DIFF_BINS / 64];
   double gF[DIFF_BINS];
   double dm[DIFF_BINS];
+  double t1[DIFF_BINS], t2[DIFF_BINS];  // a level's terms of dLoss/dF~ at k - 1 and at k
+  int kv[DIFF_BINS];                    // its branch k (-1: no terms)
 };
 
 // CDFs of one image: F~(k) = C(k) / C(l-1) with C the running sum of the
@@ -240,20 +242,38 @@ __global__ __launch_bounds__(DIFF_BINS) void k_softgrad(const uint32_t* hv, cons
     const double m = (double)k - 0.5 + (sm.u[t] - lo) / (hi - lo);
     const bool clamped = m < 0.0 || m > (double)(BINS - 1);
     const double dLdm = clamped ? 0.0 : 2.0 * G * inv3N / (double)(t ? t * (BINS - 1) : (BINS - 1));
-    sm.dm[t] = hS[t] ? dLdm : 0.0;
-    sm.gF[t] = 0.0;
+    const double dm = hS[t] ? dLdm : 0.0;
+    sm.dm[t] = dm;
+    // this level's terms of dLoss/dF~(k - 1) and dLoss/dF~(k); levels of
+    // zero weight add none
+    int kt = -1;
+    double t1 = 0.0, t2 = 0.0;
+    if (dm != 0.0) {
+      const double w = hi - lo;
+      t1 = dm * (sm.u[t] - hi) / (w * w);
+      t2 = dm * -(sm.u[t] - lo) / (w * w);
+      kt = k;
+    }
+    sm.kv[t] = kt;
+    sm.t1[t] = t1;
+    sm.t2[t] = t2;
+  }
+  __syncthreads();
+  {
+    // dLoss/dF~(t): the terms that name level t, added in level order (a
+    // level names t either as its k or as its k - 1), which is the order of
+    // one sequential sweep over the levels: the sums do not depend on the
+    // thread count
+    double g = 0.0;
+    for (int v = 0; v < BINS; ++v) {
+      const int kv = sm.kv[v];
+      if (kv == t) g += sm.t2[v];
+      else if (kv == t + 1) g += sm.t1[v];
+    }
+    sm.gF[t] = g;
   }
   __syncthreads();
   if (t == 0) {
-    // fixed order over the levels: deterministic
-    for (int v = 0; v < BINS; ++v) {
-      if (sm.dm[v] == 0.0) continue;
-      double lo, hi;
-      const int k = soft_branch(sm, sm.u[v], lo, hi);
-      const double w = hi - lo;
-      if (k > 0) sm.gF[k - 1] += sm.dm[v] * (sm.u[v] - hi) / (w * w);
-      sm.gF[k] += sm.dm[v] * -(sm.u[v] - lo) / (w * w);
-    }
     double dot = 0.0;
     for (int k = 0; k < BINS; ++k) dot += sm.gF[k] * sm.F[k];
     double suffix = 0.0;
