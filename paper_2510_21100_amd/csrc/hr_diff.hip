@@ -291,6 +291,16 @@ __global__ __launch_bounds__(DIFF_BINS) void k_softgrad(const uint32_t* hv, cons
 // reverse pass of the solve (one workgroup per image, one thread per level)
 // ---------------------------------------------------------------------------
 
+// The quantities of one forward pass that its reverse reads (the others, L^2,
+// rho and R' R, follow from these and the pass's state by one operation).
+struct PassRec {
+  float dcl[DIFF_BINS], u[DIFF_BINS], rp[DIFF_BINS], v[DIFF_BINS], lp[DIFF_BINS];
+  float Q, P, Sl, Sr;
+};
+// Passes of a checkpoint segment whose quantities are kept from its
+// recomputation for its reverse (longer segments recompute them).
+constexpr int KEEP_MAX = 10;
+
 struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   float segl[SEG_MAX][DIFF_BINS], segr[SEG_MAX][DIFF_BINS];  // states of the current segment (compacted)
   float lt[DIFF_BINS], rt[DIFF_BINS];                        // state of the pass being reversed
@@ -309,6 +319,7 @@ struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   float redv[NT_VJP / 64];
   double redd[NT_VJP / 64];
   float sc_Q, sc_P, sc_Sl, sc_Sr;
+  PassRec rec[KEEP_MAX];  // passes 0 .. E-2 of the current segment
 };
 
 // out[o] = sum_k x[k] * tab[cls(o, k)] for o < nout, k < nin: G lanes per
@@ -429,6 +440,54 @@ __device__ void vjp_forward_pass(VjpSmem& sm, const ClassLanes& cl, const SolveP
   __syncthreads();
 }
 
+__device__ void save_pass(VjpSmem& sm, PassRec& r) {
+  const int t = threadIdx.x;
+  if (t < DIFF_BINS) r.dcl[t] = sm.dcl[t];
+  if (t < sm.nB) {
+    r.u[t] = sm.u[t];
+    r.rp[t] = sm.rp[t];
+  }
+  if (t < sm.nA) {
+    r.v[t] = sm.v[t];
+    r.lp[t] = sm.lp[t];
+  }
+  if (t == 0) {
+    r.Q = sm.sc_Q;
+    r.P = sm.sc_P;
+    r.Sl = sm.sc_Sl;
+    r.Sr = sm.sc_Sr;
+  }
+}
+
+// What vjp_forward_pass leaves for the state (lt, rt), from its record: the
+// derived arrays by the same operations as there.
+__device__ void load_pass(VjpSmem& sm, const PassRec& r) {
+  const int t = threadIdx.x;
+  if (t < DIFF_BINS) {
+    const float d = r.dcl[t];
+    sm.dcl[t] = d;
+    sm.rh[t] = d > 0.f ? sm.sd[t] / d : 0.f;
+  }
+  if (t < sm.nA) {
+    sm.l2[t] = sm.lt[t] * sm.lt[t];
+    sm.v[t] = r.v[t];
+    sm.lp[t] = r.lp[t];
+  }
+  if (t < sm.nB) {
+    const float rpv = r.rp[t];
+    sm.u[t] = r.u[t];
+    sm.rp[t] = rpv;
+    sm.w[t] = rpv * sm.rt[t];
+  }
+  if (t == 0) {
+    sm.sc_Q = r.Q;
+    sm.sc_P = r.P;
+    sm.sc_Sl = r.Sl;
+    sm.sc_Sr = r.Sr;
+  }
+  __syncthreads();
+}
+
 // Reverse of one pass: (lb, rb) = adjoints of the normalised outputs on
 // entry, of the pass's input state (lt, rt) on exit.  Adds the pass's
 // contributions to dalpha, dbeta (every thread holds the same totals).
@@ -527,6 +586,7 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
   if (t < nB) sm.rb[t] = Nf * sm.tb[t];
   __syncthreads();
   double da = 0.0, db = 0.0;
+  const bool keep = E - 1 <= KEEP_MAX;
   for (int seg = ncp - 2; seg >= 0; --seg) {
     const float* c0 = ck + (size_t)seg * 2 * BINS;
     if (t < nA) sm.segl[0][t] = c0[sm.A[t]];
@@ -538,6 +598,7 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
       if (t < nB) sm.rt[t] = sm.segr[q - 1][t];
       __syncthreads();
       vjp_forward_pass(sm, cl, p);
+      if (keep) save_pass(sm, sm.rec[q - 1]);
       if (t < nA) sm.segl[q][t] = sm.lp[t] / sm.sc_Sl;
       if (t < nB) sm.segr[q][t] = sm.rp[t] / sm.sc_Sr;
       __syncthreads();
@@ -546,7 +607,10 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
       if (t < nA) sm.lt[t] = sm.segl[q][t];
       if (t < nB) sm.rt[t] = sm.segr[q][t];
       __syncthreads();
-      vjp_forward_pass(sm, cl, p);
+      if (keep && q < E - 1)
+        load_pass(sm, sm.rec[q]);
+      else
+        vjp_forward_pass(sm, cl, p);
       vjp_backward_pass(sm, cl, p, da, db);
     }
   }

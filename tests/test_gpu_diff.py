@@ -124,9 +124,13 @@ def test_softmatch_loss_and_target_gradient(H):
     ws.close()
 
 
-def test_solve_vjp_matches_the_reference(H):
+# checkpoint intervals: the default; one pass per segment; the longest
+# segments whose forward quantities the reverse keeps (10 passes after the
+# checkpoint) and the shortest it recomputes; the longest allowed
+@pytest.mark.parametrize("iters,every", [(K, EVERY), (30, 1), (33, 11), (24, 12), (32, 16)])
+def test_solve_vjp_matches_the_reference(H, iters, every):
     H, diff = H
-    cases = _images(SHAPES)
+    cases = _images(SHAPES if every == EVERY else SHAPES[:2])
     hs = [_hists(img) for img, _ in cases]
     hv = torch.from_numpy(np.stack([a for a, _ in hs]).astype(np.int32)).cuda()
     hg = torch.from_numpy(np.stack([b for _, b in hs]).astype(np.int32)).cuda()
@@ -136,10 +140,10 @@ def test_solve_vjp_matches_the_reference(H):
     for i, (hS, hG) in enumerate(hs):
         a = torch.tensor(PARAMS.alpha, dtype=torch.float64, requires_grad=True)
         b = torch.tensor(PARAMS.beta, dtype=torch.float64, requires_grad=True)
-        target = diff.TargetFn.apply(a, b, hv[i:i + 1], hg[i:i + 1], K, PARAMS.gamma, EVERY, ws)
+        target = diff.TargetFn.apply(a, b, hv[i:i + 1], hg[i:i + 1], iters, PARAMS.gamma, every, ws)
         (target * torch.from_numpy(cot[i:i + 1].astype(np.float32)).cuda()).sum().backward()
         torch.cuda.synchronize()
-        da, db = REF.target_vjp(hS, hG, PARAMS.alpha, PARAMS.beta, PARAMS.gamma, K, cot[i])
+        da, db = REF.target_vjp(hS, hG, PARAMS.alpha, PARAMS.beta, PARAMS.gamma, iters, cot[i])
         assert abs(float(a.grad) - da) <= GRAD_REL * abs(da), (i, float(a.grad), da)
         assert abs(float(b.grad) - db) <= GRAD_REL * abs(db), (i, float(b.grad), db)
     ws.close()
