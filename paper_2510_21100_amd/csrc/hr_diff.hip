@@ -336,7 +336,20 @@ __device__ inline void lane_gather(int nout, int nin, const float* x, const floa
     const int o = min(q / G, nout - 1), k = q & (G - 1);
     const int k0 = k * L, k1 = min(k0 + L, nin);
     float a4[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int kk = k0; kk < k1; ++kk) a4[(kk - k0) & 3] = fmaf(x[kk], tab[cls(o, kk)], a4[(kk - k0) & 3]);
+    int kk = k0;
+    // four inputs at a time, their reads issued together; input kk always
+    // goes to partial sum (kk - k0) mod 4
+    for (; kk + 4 <= k1; kk += 4) {
+      float xv[4], tv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xv[u] = x[kk + u];
+        tv[u] = tab[cls(o, kk + u)];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = fmaf(xv[u], tv[u], a4[u]);
+    }
+    for (; kk < k1; ++kk) a4[(kk - k0) & 3] = fmaf(x[kk], tab[cls(o, kk)], a4[(kk - k0) & 3]);
     float acc = group_sum_last((a4[0] + a4[1]) + (a4[2] + a4[3]), G);
     if (k == G - 1 && q / G < nout) out[o] = acc;
   }
