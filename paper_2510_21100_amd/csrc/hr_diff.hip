@@ -62,6 +62,8 @@ struct SoftSmem {
   double dm[DIFF_BINS];
   double t1[DIFF_BINS], t2[DIFF_BINS];  // a level's terms of dLoss/dF~ at k - 1 and at k
   int kv[DIFF_BINS];                    // its branch k (-1: no terms)
+  double suf[DIFF_BINS];                // suffix sums of dLoss/dF~
+  double dot;                           // sum of dLoss/dF~(k) F~(k)
 };
 
 // CDFs of one image: F~(k) = C(k) / C(l-1) with C the running sum of the
@@ -265,26 +267,36 @@ __global__ __launch_bounds__(DIFF_BINS) void k_softgrad(const uint32_t* hv, cons
     // one sequential sweep over the levels: the sums do not depend on the
     // thread count
     double g = 0.0;
-    for (int v = 0; v < BINS; ++v) {
-      const int kv = sm.kv[v];
-      if (kv == t) g += sm.t2[v];
-      else if (kv == t + 1) g += sm.t1[v];
+    for (int v0 = 0; v0 < BINS; v0 += 16) {
+      int kvv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) kvv[u] = sm.kv[v0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (kvv[u] == t) g += sm.t2[v0 + u];
+        else if (kvv[u] == t + 1) g += sm.t1[v0 + u];
+      }
     }
     sm.gF[t] = g;
   }
   __syncthreads();
+  // the normalisation F~ = C / C(l-1): the dot product and the suffix sums
+  // are sequential (one thread, fixed order); the divisions are per level
   if (t == 0) {
     double dot = 0.0;
+#pragma unroll 16
     for (int k = 0; k < BINS; ++k) dot += sm.gF[k] * sm.F[k];
     double suffix = 0.0;
+#pragma unroll 16
     for (int k = BINS - 1; k >= 0; --k) {
       suffix += sm.gF[k];
-      sm.dm[k] = (suffix - dot) / S;
+      sm.suf[k] = suffix;
     }
+    sm.dot = dot;
     loss[i] = (double)(long long)a[BINS] / LOSS_SCALE * inv3N;
   }
   __syncthreads();
-  dtarget[(size_t)i * BINS + t] = (float)sm.dm[t];
+  dtarget[(size_t)i * BINS + t] = (float)((sm.suf[t] - sm.dot) / S);
 }
 
 // ---------------------------------------------------------------------------
