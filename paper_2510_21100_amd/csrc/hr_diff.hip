@@ -34,6 +34,30 @@ constexpr int SEG_MAX = 16;   // largest checkpoint interval
 constexpr double G_SCALE = 16777216.0;       // 2^24: fixed point of G[v]
 constexpr double LOSS_SCALE = 4294967296.0;  // 2^32: fixed point of the squared errors
 
+// Two block sums for the barriers of one: each value is summed exactly as
+// block_sum sums it (wave sum, then the waves in order).
+template <int NT, typename T, typename U>
+__device__ inline void block_sum2(T& x, U& y, T* redx, U* redy) {
+  x = wave_sum(x);
+  y = wave_sum(y);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    redx[w] = x;
+    redy[w] = y;
+  }
+  __syncthreads();
+  T sx = redx[0];
+  U sy = redy[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) {
+    sx += redx[i];
+    sy += redy[i];
+  }
+  x = sx;
+  y = sy;
+}
+
 // ---------------------------------------------------------------------------
 // forward with checkpoints: one workgroup per image
 // ---------------------------------------------------------------------------
@@ -328,7 +352,7 @@ struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   double theta[DIFF_BINS];                           // Eq. (17) on A
   double qc1[DIFF_BINS + 1], qc2[DIFF_BINS + 1];     // running sums over B (class sums)
   double part[NT_VJP];                               // lane partials of the class sums
-  float redv[NT_VJP / 64];
+  float redv[NT_VJP / 64], redv2[NT_VJP / 64];
   double redd[NT_VJP / 64];
   float sc_Q, sc_P, sc_Sl, sc_Sr;
   PassRec rec[KEEP_MAX];  // passes 0 .. E-2 of the current segment
@@ -446,8 +470,8 @@ __device__ void vjp_forward_pass(VjpSmem& sm, const ClassLanes& cl, const SolveP
     sm.rp[t] = rpv;
     sm.w[t] = rpv * sm.rt[t];
   }
-  const float Sr = block_sum<NT_VJP>(rpv, sm.redv);
-  const float P = block_sum<NT_VJP>(rpv * rpv, sm.redv);
+  float Sr = rpv, P = rpv * rpv;
+  block_sum2<NT_VJP>(Sr, P, sm.redv, sm.redv2);
   row_gather(sm, sm.w, sm.rh, sm.v, IdxClass{sm});
   __syncthreads();
   float lpv = 0.f;
@@ -523,14 +547,16 @@ __device__ void vjp_backward_pass(VjpSmem& sm, const ClassLanes& cl, const Solve
   const float Q = sm.sc_Q, P = sm.sc_P, Sl = sm.sc_Sl, Sr = sm.sc_Sr;
   const float Dl = P + p.alpha, Dr = Q + p.beta;
   // Eqs. (14), (15): L+ = L'/Sl, R+ = R'/Sr
-  const float dotl = block_sum<NT_VJP>(t < nA ? sm.lb[t] * sm.lp[t] / Sl : 0.f, sm.redv);
-  const float dotr = block_sum<NT_VJP>(t < nB ? sm.rb[t] * sm.rp[t] / Sr : 0.f, sm.redv);
+  float dotl = t < nA ? sm.lb[t] * sm.lp[t] / Sl : 0.f, dotr = t < nB ? sm.rb[t] * sm.rp[t] / Sr : 0.f;
+  block_sum2<NT_VJP>(dotl, dotr, sm.redv, sm.redv2);
   float lbp = 0.f, rbp = 0.f;
   if (t < nA) lbp = (sm.lb[t] - dotl) / Sl;
   if (t < nB) rbp = (sm.rb[t] - dotr) / Sr;
   // Eq. (12): L' = (L v + alpha s) / (P + alpha)
-  const double da = block_sum<NT_VJP>(t < nA ? (double)lbp * (double)(sm.sc[t] - sm.lp[t]) / Dl : 0.0, sm.redd);
-  const float Pb = -block_sum<NT_VJP>(t < nA ? lbp * sm.lp[t] / Dl : 0.f, sm.redv);
+  double da = t < nA ? (double)lbp * (double)(sm.sc[t] - sm.lp[t]) / Dl : 0.0;
+  float Pb = t < nA ? lbp * sm.lp[t] / Dl : 0.f;
+  block_sum2<NT_VJP>(da, Pb, sm.redd, sm.redv);
+  Pb = -Pb;
   dalpha += da;
   if (t < nA) {
     sm.vb[t] = lbp * sm.lt[t] / Dl;
@@ -547,8 +573,10 @@ __device__ void vjp_backward_pass(VjpSmem& sm, const ClassLanes& cl, const Solve
     sm.rbp[t] = rbp;
   }
   // Eq. (13): R' = (R u + beta g) / (Q + beta)
-  const double db = block_sum<NT_VJP>(t < nB ? (double)rbp * (double)(sm.gc[t] - sm.rp[t]) / Dr : 0.0, sm.redd);
-  const float Qb = -block_sum<NT_VJP>(t < nB ? rbp * sm.rp[t] / Dr : 0.f, sm.redv);
+  double db = t < nB ? (double)rbp * (double)(sm.gc[t] - sm.rp[t]) / Dr : 0.0;
+  float Qb = t < nB ? rbp * sm.rp[t] / Dr : 0.f;
+  block_sum2<NT_VJP>(db, Qb, sm.redd, sm.redv);
+  Qb = -Qb;
   dbeta += db;
   if (t < nB) {
     sm.ub[t] = rbp * sm.rt[t] / Dr;
