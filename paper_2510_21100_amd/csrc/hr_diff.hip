@@ -353,7 +353,7 @@ struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   double qc1[DIFF_BINS + 1], qc2[DIFF_BINS + 1];     // running sums over B (class sums)
   double part[NT_VJP];                               // lane partials of the class sums
   float redv[NT_VJP / 64], redv2[NT_VJP / 64];
-  double redd[NT_VJP / 64];
+  double redd[NT_VJP / 64], redd2[NT_VJP / 64];
   float sc_Q, sc_P, sc_Sl, sc_Sr;
   PassRec rec[KEEP_MAX];  // passes 0 .. E-2 of the current segment
 };
@@ -403,6 +403,48 @@ __device__ inline void row_gather(const VjpSmem& sm, const float* y, const float
   lane_gather(sm.nA, sm.nB, y, tab, out, [&](int i, int j) { return cls(i, j); });
 }
 
+// Exclusive prefix sums, in FP64, of q1[0..n) followed by a zero (n + 1
+// values) into dst, and of q2 into dst2 when given: block_scan's ranges,
+// wave scans and order over the waves, reading the inputs where they are
+// (no staging copy and barrier before the scan).
+template <int NT>
+__device__ inline void scan_levels(const float* q1, const float* q2, int n, double* dst, double* dst2, double* r1,
+                                   double* r2) {
+  const int t = threadIdx.x;
+  const int m = n + 1;
+  const int per = (m + NT - 1) / NT;
+  const int b0 = min(t * per, m), b1 = min(b0 + per, m);
+  double l1 = 0.0, l2 = 0.0;
+  for (int i = b0; i < b1; ++i) {
+    l1 += i < n ? (double)q1[i] : 0.0;
+    if (q2) l2 += i < n ? (double)q2[i] : 0.0;
+  }
+  const int lane = t & 63;
+  const double i1 = wave_scan(l1);
+  const double i2 = q2 ? wave_scan(l2) : 0.0;
+  __syncthreads();
+  if (lane == 63) {
+    r1[t >> 6] = i1;
+    if (q2) r2[t >> 6] = i2;
+  }
+  __syncthreads();
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = 0; i < (t >> 6); ++i) {
+    s1 += r1[i];
+    if (q2) s2 += r2[i];
+  }
+  double run1 = s1 + i1 - l1, run2 = s2 + i2 - l2;
+  for (int i = b0; i < b1; ++i) {
+    dst[i] = run1;
+    run1 += i < n ? (double)q1[i] : 0.0;
+    if (q2) {
+      dst2[i] = run2;
+      run2 += i < n ? (double)q2[i] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
 // out[m] = sum over the cells (i, j) of class m of p1[i] q1[j] + p2[i] q2[j]
 // (the second term only with TWO); classes with s_m = 0 get 0.  Rows of a
 // class contribute runs of B, summed as differences of FP64 running sums of
@@ -413,14 +455,8 @@ __device__ inline void class_sums(VjpSmem& sm, const ClassLanes& cl, const float
                                   const float* p2, const float* q2, float* out) {
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
-  for (int j = t; j <= nB; j += NT_VJP) {
-    sm.qc1[j] = j < nB ? (double)q1[j] : 0.0;
-    if (TWO) sm.qc2[j] = j < nB ? (double)q2[j] : 0.0;
-  }
   for (int m = t; m < DIFF_BINS; m += NT_VJP) out[m] = 0.f;
-  __syncthreads();
-  block_scan<NT_VJP, double>(sm.qc1, nB + 1, sm.redd);
-  if (TWO) block_scan<NT_VJP, double>(sm.qc2, nB + 1, sm.redd);
+  scan_levels<NT_VJP>(q1, TWO ? q2 : nullptr, nB, sm.qc1, sm.qc2, sm.redd, sm.redd2);
   double acc = 0.0;
   if (cl.q >= 0) {
     const int m = sm.A[cl.q];
@@ -443,7 +479,9 @@ __device__ inline void class_sums(VjpSmem& sm, const ClassLanes& cl, const float
 
 struct IdxClass {
   const VjpSmem& sm;
-  __device__ int operator()(int i, int j) const { return class_of<DIFF_BINS>(sm.A[i], sm.B[j]); }
+  // the FP32 form of index(a, b): the same class as the integer formula for
+  // every pair of levels at 256 levels
+  __device__ int operator()(int i, int j) const { return (int)class_of(sm.af[i], sm.bq[j]); }
 };
 struct Idx1Class {
   const VjpSmem& sm;
@@ -624,6 +662,10 @@ __global__ __launch_bounds__(NT_VJP) void k_solve_vjp(const uint32_t* hv, const 
     sm.theta[t] = a ? pow((double)a / (double)(BINS - 1), p.inv_gamma) : 0.0;  // Eq. (17)
   }
   if (t < BINS) sm.gH[t] = dtarget[(size_t)img * BINS + t];
+  if (t < BINS) {
+    sm.af[t] = t < nA ? (float)sm.A[t] : 0.f;
+    sm.bq[t] = t < nB ? (float)sm.B[t] / (float)(BINS - 1) : 0.f;
+  }
   const ClassLanes cl = class_lanes<NT_VJP>(nA, t);
   // final state
   const float* last = ck + (size_t)(ncp - 1) * 2 * BINS;
