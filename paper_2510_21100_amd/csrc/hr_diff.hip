@@ -353,7 +353,7 @@ struct VjpSmem : SolveCore<DIFF_BINS, NT_VJP> {
   double qc1[DIFF_BINS + 1], qc2[DIFF_BINS + 1];     // running sums over B (class sums)
   double part[NT_VJP];                               // lane partials of the class sums
   float redv[NT_VJP / 64], redv2[NT_VJP / 64];
-  double redd[NT_VJP / 64], redd2[NT_VJP / 64];
+  double redd[NT_VJP / 64];
   float sc_Q, sc_P, sc_Sl, sc_Sr;
   PassRec rec[KEEP_MAX];  // passes 0 .. E-2 of the current segment
 };
@@ -404,42 +404,33 @@ __device__ inline void row_gather(const VjpSmem& sm, const float* y, const float
 }
 
 // Exclusive prefix sums, in FP64, of q1[0..n) followed by a zero (n + 1
-// values) into dst, and of q2 into dst2 when given: block_scan's ranges,
-// wave scans and order over the waves, reading the inputs where they are
-// (no staging copy and barrier before the scan).
+// values) into dst, and of q2 into dst2 when given, in the association order
+// of block_scan over NT threads with one value per thread (n + 1 <= NT):
+// chunks of 64 values scanned by wave sums, each chunk offset by the totals
+// of the chunks before it added in order.  Wave 0 does all of it, so no
+// barrier is needed before the scan, one after.
 template <int NT>
-__device__ inline void scan_levels(const float* q1, const float* q2, int n, double* dst, double* dst2, double* r1,
-                                   double* r2) {
+__device__ inline void scan_levels(const float* q1, const float* q2, int n, double* dst, double* dst2) {
+  static_assert(DIFF_BINS + 1 <= NT, "one value per thread of the block form");
   const int t = threadIdx.x;
   const int m = n + 1;
-  const int per = (m + NT - 1) / NT;
-  const int b0 = min(t * per, m), b1 = min(b0 + per, m);
-  double l1 = 0.0, l2 = 0.0;
-  for (int i = b0; i < b1; ++i) {
-    l1 += i < n ? (double)q1[i] : 0.0;
-    if (q2) l2 += i < n ? (double)q2[i] : 0.0;
-  }
-  const int lane = t & 63;
-  const double i1 = wave_scan(l1);
-  const double i2 = q2 ? wave_scan(l2) : 0.0;
-  __syncthreads();
-  if (lane == 63) {
-    r1[t >> 6] = i1;
-    if (q2) r2[t >> 6] = i2;
-  }
-  __syncthreads();
-  double s1 = 0.0, s2 = 0.0;
-  for (int i = 0; i < (t >> 6); ++i) {
-    s1 += r1[i];
-    if (q2) s2 += r2[i];
-  }
-  double run1 = s1 + i1 - l1, run2 = s2 + i2 - l2;
-  for (int i = b0; i < b1; ++i) {
-    dst[i] = run1;
-    run1 += i < n ? (double)q1[i] : 0.0;
-    if (q2) {
-      dst2[i] = run2;
-      run2 += i < n ? (double)q2[i] : 0.0;
+  if (t < 64) {
+    double base1 = 0.0, base2 = 0.0;
+    for (int c = 0; c * 64 < m; ++c) {
+      const int i = c * 64 + t;
+      double l1 = 0.0, l2 = 0.0;
+      if (i < m) {
+        l1 += i < n ? (double)q1[i] : 0.0;
+        if (q2) l2 += i < n ? (double)q2[i] : 0.0;
+      }
+      const double i1 = wave_scan(l1);
+      const double i2 = q2 ? wave_scan(l2) : 0.0;
+      if (i < m) {
+        dst[i] = base1 + i1 - l1;
+        if (q2) dst2[i] = base2 + i2 - l2;
+      }
+      base1 += read_lane(i1, 63);
+      if (q2) base2 += read_lane(i2, 63);
     }
   }
   __syncthreads();
@@ -456,7 +447,7 @@ __device__ inline void class_sums(VjpSmem& sm, const ClassLanes& cl, const float
   const int t = threadIdx.x;
   const int nA = sm.nA, nB = sm.nB;
   for (int m = t; m < DIFF_BINS; m += NT_VJP) out[m] = 0.f;
-  scan_levels<NT_VJP>(q1, TWO ? q2 : nullptr, nB, sm.qc1, sm.qc2, sm.redd, sm.redd2);
+  scan_levels<NT_VJP>(q1, TWO ? q2 : nullptr, nB, sm.qc1, sm.qc2);
   double acc = 0.0;
   if (cl.q >= 0) {
     const int m = sm.A[cl.q];
