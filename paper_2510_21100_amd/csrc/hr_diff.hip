@@ -461,8 +461,17 @@ __device__ inline void class_sums(VjpSmem& sm, const ClassLanes& cl, const float
   sm.part[t] = acc;
   __syncthreads();
   if (cl.q >= 0 && cl.k == 0) {
+    // the class's lane partials in lane order, read eight at a time
     double d = 0.0;
-    for (int x = 0; x < cl.g; ++x) d += sm.part[t + x];
+    int x = 0;
+    for (; x + 8 <= cl.g; x += 8) {
+      double pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = sm.part[t + x + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d += pv[u];
+    }
+    for (; x < cl.g; ++x) d += sm.part[t + x];
     out[sm.A[cl.q]] = (float)d;
   }
   __syncthreads();
